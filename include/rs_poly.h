@@ -1,0 +1,147 @@
+/*
+ * rs_poly.h -- C ABI of librs_poly.so: polynomial (generator-polynomial)
+ * Reed-Solomon RS(k,m) erasure coding over GF(2^w) on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operations follow the paper "On the Effectiveness of Polynomial
+ * Realization of Reed-Solomon Codes for Storage Systems" (Sheykh Esmaili,
+ * Datta):
+ *   - Sec. 1: an object of k symbols is encoded into n = k + m blocks so that
+ *     any k of the n blocks recreate it; symbols live in GF(2^w);
+ *   - Sec. 3.1: g(x) = (x + alpha^0)(x + alpha^1)...(x + alpha^(m-1)), with
+ *     primitive root alpha = 2;
+ *   - Sec. 3.2, eq. (1)-(2): the parity symbols are the coefficients of
+ *     x^m d(x) mod g(x), data symbol d_j on degree m+j, parity p_i on degree i;
+ *   - Sec. 3.3: decoding evaluates the received word, erasures dropped, at
+ *     the roots of g (step 1) and solves the Vandermonde system in the erased
+ *     symbols (step 2), with the matrix inverted once per erasure pattern
+ *     (Opt3 of Sec. 4).
+ *
+ * Stripe and block layout.  A stripe is n blocks of block_bytes bytes each.
+ * Byte column c of the stripe (byte c of every block) is one codeword.  The
+ * API numbers blocks 0..n-1: block b < k is data d_b, block b >= k is parity
+ * p_(b-k).  Symbols are stored one per byte; for w = 4 only the low nibble is
+ * used and the high nibble must be zero (other bytes give unspecified output
+ * but are memory-safe).
+ *
+ * Memory and ownership.  Block pointers are DEVICE pointers (e.g. from
+ * hipMalloc or torch.empty(..., device="cuda").data_ptr()) on the device that
+ * is current when the call is made; the arrays holding them are HOST arrays
+ * read during the call only.  The caller owns every block buffer.  The
+ * library owns the code handle and everything hung off it (tables, the
+ * per-erasure-pattern coefficient cache, batch descriptors, graphs), released
+ * by the matching *_free call.  Full speed needs 16-byte-aligned block
+ * pointers and block sizes that are a multiple of 16; any alignment and size
+ * is accepted, smaller alignments take slower load paths.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the legacy
+ * default stream).  Encode and decode are asynchronous: they enqueue work on
+ * `stream` and return; results are valid once the stream has synchronized.
+ * A handle may be used from several host threads; calls are serialized
+ * inside the library.
+ *
+ * Errors.  Every call returns 0 (RS_OK) or a negative RS_E* code.  Arguments
+ * are validated on the host before any HIP call is made, so a rejected call
+ * has no effect.  RS_EDEVICE reports a HIP runtime error; an asynchronous
+ * device fault of earlier work can surface as RS_EDEVICE on a later call.
+ */
+#ifndef RS_POLY_H
+#define RS_POLY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RS_POLY_MAX_M 8      /* most parity blocks a code may have        */
+#define RS_POLY_MAX_N 255    /* n = k + m must stay below 2^w (Sec. 1)     */
+
+/* Status codes. */
+#define RS_OK         0
+#define RS_EINVAL    -1   /* bad k, m, w, field polynomial, flags or size  */
+#define RS_ERANGE    -2   /* erasure index outside [0,n) or repeated       */
+#define RS_ETOOMANY  -3   /* more erasures than parity blocks (t > m)      */
+#define RS_ENULL     -4   /* a required pointer is NULL                    */
+#define RS_EDEVICE   -5   /* HIP runtime error                             */
+#define RS_ENOMEM    -6   /* host or device allocation failed              */
+#define RS_EBUSY     -7   /* resource in use (e.g. a full serving queue)   */
+
+/* Decode flag: read every surviving block (n - t of them) instead of the
+ * minimum k.  Sec. 3.3 remarks that decoding may use more than k survivors;
+ * the output is identical, only the bytes read differ. */
+#define RS_POLY_FLAG_ALL_SURVIVORS 1u
+
+typedef struct rs_poly rs_poly_t;
+
+/* Creates a code handle for RS(k,m) over GF(2^w).  Host only: no HIP call is
+ * made, no device memory is allocated.
+ *   k          data blocks, k >= 1
+ *   m          parity blocks, 1 <= m <= RS_POLY_MAX_M
+ *   w          symbol width in bits, 4 or 8
+ *   prim_poly  field polynomial with bit w set, e.g. 0x11D (w=8) or 0x13 (w=4);
+ *              it must be primitive, i.e. alpha = 2 = x generates the field
+ *              (Sec. 3.1 example: "the primitive root is 2")
+ *   out        receives the handle
+ * Errors: RS_ENULL (out), RS_EINVAL (k, m, w or prim_poly, or k+m > 2^w - 1:
+ * the n positions alpha^pos must be distinct), RS_ENOMEM. */
+int rs_poly_init(int k, int m, int w, unsigned prim_poly, rs_poly_t **out);
+
+/* Releases the handle and everything it owns.  Waits for nothing: the
+ * caller must not free a handle with its work still queued.  NULL is a
+ * no-op. */
+void rs_poly_free(rs_poly_t *h);
+
+/* Static message for a status code; never NULL. */
+const char *rs_poly_strerror(int err);
+
+/* Copies the m+1 coefficients of g(x) (Sec. 3.1), low degree first, into g.
+ * Host only.  Errors: RS_ENULL. */
+int rs_poly_generator(const rs_poly_t *h, uint8_t *g);
+
+/* Encode (Sec. 3.2, eq. (1)-(2)): for every byte column c < block_bytes,
+ * parity[i][c] = coefficient i of x^m * sum_j data[j][c] x^j mod g(x).
+ *   data     host array of k device pointers to the data blocks (read only)
+ *   parity   host array of m device pointers to the parity blocks (written)
+ *   block_bytes  bytes per block; 0 is a successful no-op
+ * Parity buffers must not overlap data buffers.
+ * Errors: RS_ENULL (h, data, parity, or any of their entries), RS_EDEVICE. */
+int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data,
+                   uint8_t *const *parity, size_t block_bytes, void *stream);
+
+/* Erasure decode (Sec. 3.3): rebuilds, in place, exactly the blocks named in
+ * erasures[0..n_erasures), data or parity, from the surviving blocks.
+ *   blocks      host array of n = k+m device pointers, API block order
+ *   erasures    API indices of the lost blocks, any order, no repeats
+ *   n_erasures  t, 0 <= t <= m; t = 0 is a successful no-op
+ *   flags       0 or RS_POLY_FLAG_ALL_SURVIVORS
+ * Erased buffers are outputs only and are never read.  By default the
+ * library reads k survivors (all surviving data blocks first, then the
+ * lowest-numbered surviving parity blocks) and may leave the other m - t
+ * surviving blocks unread; their pointers may then be NULL.
+ * Errors: RS_ENULL, RS_EINVAL (n_erasures < 0, unknown flags),
+ * RS_ETOOMANY (t > m), RS_ERANGE, RS_EDEVICE. */
+int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
+                   const int *erasures, int n_erasures, unsigned flags,
+                   void *stream);
+
+/* Host-only view of the decode plan for an erasure pattern (the per-pattern
+ * coefficients of Sec. 3.3 step 2, cached as Opt3 of Sec. 4 describes).
+ *   read_set   receives the API indices of the blocks decode reads, in
+ *              increasing order (capacity n); may be NULL
+ *   n_read     receives their count; may be NULL
+ *   coeffs     receives the t x m matrix C (row-major): rebuilt symbol e is
+ *              sum_l C[e][l] * r_l, where r(x) = sum_l r_l x^l is the received
+ *              word (erased and unread symbols set to 0) reduced mod g(x);
+ *              may be NULL
+ * Errors: as rs_poly_decode's validation. */
+int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures,
+                        unsigned flags, int *read_set, int *n_read,
+                        uint8_t *coeffs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_POLY_H */

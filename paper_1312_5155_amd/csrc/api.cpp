@@ -1,0 +1,235 @@
+// C ABI of librs_poly.so: code handles, plain (one stripe per launch)
+// encode and decode.  Validation happens here, on the host, before any HIP
+// call.
+#include <hip/hip_runtime_api.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+
+#include "../../include/rs_poly.h"
+#include "gf.h"
+#include "rs_internal.h"
+#include "runtime.h"
+
+struct rs_poly {
+  rsp::Code code;
+  std::mutex mu;
+};
+
+namespace rsp {
+
+int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  static std::mutex mu;
+  static int cache[64] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0 || dev >= 64) return -1;
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -1;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+int pointer_alignment(const void *p) {
+  const uintptr_t v = reinterpret_cast<uintptr_t>(p);
+  if ((v & 15) == 0) return 16;
+  if ((v & 7) == 0) return 8;
+  if ((v & 3) == 0) return 4;
+  return 1;
+}
+
+LaunchCfg default_cfg(Mode mode, uint64_t B, int min_align, int num_cu) {
+  LaunchCfg cfg{};
+  cfg.threads = mode == kDecode ? 1024 : 512;
+  if (min_align < 4) {
+    cfg.bytewise = true;
+    cfg.dwords_per_lane = 1;
+  } else {
+    // Widest loads that still give every CU a few thousand lanes of work.
+    const uint64_t want_lanes = (uint64_t)num_cu * 1024;
+    int w = std::min(4, min_align / 4);
+    while (w > 1 && (B + 4 * w - 1) / (4 * w) < want_lanes) w /= 2;
+    cfg.dwords_per_lane = w;
+  }
+  const uint64_t cols = 4ull * cfg.dwords_per_lane;
+  const uint64_t chunks = (B + cols - 1) / cols;
+  const uint64_t wgs = (chunks + cfg.threads - 1) / cfg.threads;
+  const uint64_t resident = (uint64_t)num_cu * codec_wgs_per_cu(mode);
+  cfg.grid = (int)std::max<uint64_t>(1, std::min(wgs, resident));
+  return cfg;
+}
+
+int hip_status(int err) { return err == 0 ? RS_OK : RS_EDEVICE; }
+
+int validate_erasures(const Code &c, const int *e, int t, unsigned flags, int *sorted_out) {
+  if (flags & ~RS_POLY_FLAG_ALL_SURVIVORS) return RS_EINVAL;
+  if (t < 0) return RS_EINVAL;
+  if (t > c.m()) return RS_ETOOMANY;
+  if (t > 0 && !e) return RS_ENULL;
+  for (int i = 0; i < t; ++i) {
+    if (e[i] < 0 || e[i] >= c.n()) return RS_ERANGE;
+    sorted_out[i] = e[i];
+  }
+  std::sort(sorted_out, sorted_out + t);
+  for (int i = 1; i < t; ++i)
+    if (sorted_out[i] == sorted_out[i - 1]) return RS_ERANGE;
+  return RS_OK;
+}
+
+static int round_up(int x, int to) { return (x + to - 1) / to * to; }
+
+void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *const *parity,
+                        uint64_t B, CodecParams *p) {
+  for (int j = 0; j < c.k(); ++j) p->data[j] = data[j];
+  for (int i = 0; i < c.m(); ++i) p->out[i] = parity[i];
+  p->block_bytes = B;
+  p->k = c.k();
+  p->m = c.m();
+  p->k_pad = round_up(c.k(), c.state_bytes());
+  p->n_out = c.m();
+  memcpy(p->lfsr_basis, c.lfsr_basis(), sizeof(p->lfsr_basis));
+}
+
+void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
+                        const int *sorted, int t, uint64_t B, CodecParams *p) {
+  for (int b : plan.read) {
+    if (b < c.k())
+      p->data[b] = blocks[b];
+    else
+      p->par_in[b - c.k()] = blocks[b];
+  }
+  for (int r = 0; r < t; ++r) p->out[r] = blocks[sorted[r]];
+  p->block_bytes = B;
+  p->k = c.k();
+  p->m = c.m();
+  p->k_pad = round_up(c.k(), c.state_bytes());
+  p->n_out = t;
+  memcpy(p->lfsr_basis, c.lfsr_basis(), sizeof(p->lfsr_basis));
+  memcpy(p->apply_basis, plan.apply_basis, sizeof(p->apply_basis));
+}
+
+}  // namespace rsp
+
+using namespace rsp;
+
+extern "C" {
+
+int rs_poly_init(int k, int m, int w, unsigned prim_poly, rs_poly_t **out) {
+  if (!out) return RS_ENULL;
+  *out = nullptr;
+  rs_poly_t *h = new (std::nothrow) rs_poly_t;
+  if (!h) return RS_ENOMEM;
+  const int rc = h->code.init(k, m, w, prim_poly);
+  if (rc != RS_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return RS_OK;
+}
+
+void rs_poly_free(rs_poly_t *h) { delete h; }
+
+const char *rs_poly_strerror(int err) {
+  switch (err) {
+    case RS_OK: return "success";
+    case RS_EINVAL: return "invalid argument (code parameters, flags or size)";
+    case RS_ERANGE: return "erasure index out of range or repeated";
+    case RS_ETOOMANY: return "more erasures than parity blocks";
+    case RS_ENULL: return "required pointer is NULL";
+    case RS_EDEVICE: return "HIP runtime error";
+    case RS_ENOMEM: return "out of memory";
+    case RS_EBUSY: return "resource busy";
+    default: return "unknown status";
+  }
+}
+
+int rs_poly_generator(const rs_poly_t *h, uint8_t *g) {
+  if (!h || !g) return RS_ENULL;
+  memcpy(g, h->code.generator(), (size_t)h->code.m() + 1);
+  return RS_OK;
+}
+
+int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data, uint8_t *const *parity,
+                   size_t block_bytes, void *stream) {
+  if (!h || !data || !parity) return RS_ENULL;
+  const Code &c = h->code;
+  int align = 16;
+  for (int j = 0; j < c.k(); ++j) {
+    if (!data[j]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(data[j]));
+  }
+  for (int i = 0; i < c.m(); ++i) {
+    if (!parity[i]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(parity[i]));
+  }
+  if (block_bytes == 0) return RS_OK;
+
+  CodecParams p;
+  memset(&p, 0, sizeof(p));
+  fill_encode_params(c, data, parity, block_bytes, &p);
+  std::lock_guard<std::mutex> lock(h->mu);
+  const int ncu = device_cu_count();
+  if (ncu <= 0) return RS_EDEVICE;
+  const LaunchCfg cfg = default_cfg(kEncode, block_bytes, align, ncu);
+  return hip_status(launch_codec(kEncode, c.state_bytes(), p, cfg, stream));
+}
+
+int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
+                   const int *erasures, int n_erasures, unsigned flags, void *stream) {
+  if (!h) return RS_ENULL;
+  int sorted[kMaxM];
+  const int rc = validate_erasures(h->code, erasures, n_erasures, flags, sorted);
+  if (rc != RS_OK) return rc;
+  if (n_erasures == 0) return RS_OK;
+  if (!blocks) return RS_ENULL;
+  auto plan = h->code.plan(sorted, n_erasures, flags);
+  int align = 16;
+  for (int b : plan->read) {
+    if (!blocks[b]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(blocks[b]));
+  }
+  for (int i = 0; i < n_erasures; ++i) {
+    if (!blocks[sorted[i]]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(blocks[sorted[i]]));
+  }
+  if (block_bytes == 0) return RS_OK;
+
+  CodecParams p;
+  memset(&p, 0, sizeof(p));
+  fill_decode_params(h->code, *plan, blocks, sorted, n_erasures, block_bytes, &p);
+  std::lock_guard<std::mutex> lock(h->mu);
+  const int ncu = device_cu_count();
+  if (ncu <= 0) return RS_EDEVICE;
+  const LaunchCfg cfg = default_cfg(kDecode, block_bytes, align, ncu);
+  return hip_status(launch_codec(kDecode, h->code.state_bytes(), p, cfg, stream));
+}
+
+int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures, unsigned flags,
+                        int *read_set, int *n_read, uint8_t *coeffs) {
+  if (!h) return RS_ENULL;
+  int sorted[kMaxM];
+  const int rc = validate_erasures(h->code, erasures, n_erasures, flags, sorted);
+  if (rc != RS_OK) return rc;
+  auto plan = h->code.plan(sorted, n_erasures, flags);
+  if (read_set)
+    for (size_t i = 0; i < plan->read.size(); ++i) read_set[i] = plan->read[i];
+  if (n_read) *n_read = (int)plan->read.size();
+  if (coeffs) {
+    // Rows in the caller's order of the erasure list.
+    const int m = h->code.m();
+    for (int i = 0; i < n_erasures; ++i) {
+      const int r = (int)(std::find(sorted, sorted + n_erasures, erasures[i]) - sorted);
+      memcpy(coeffs + (size_t)i * m, plan->coeffs.data() + (size_t)r * m, (size_t)m);
+    }
+  }
+  return RS_OK;
+}
+
+}  // extern "C"

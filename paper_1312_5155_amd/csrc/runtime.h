@@ -1,0 +1,31 @@
+// Helpers shared by the C-ABI entry points: validation, kernel-argument
+// filling and default launch shapes.
+#pragma once
+
+#include <stdint.h>
+
+#include "gf.h"
+#include "rs_internal.h"
+
+namespace rsp {
+
+// CUs of the current device (cached); -1 on a HIP error.
+int device_cu_count();
+// Largest of 16, 8, 4, 1 that divides the address.
+int pointer_alignment(const void *p);
+// Launch shape for one stripe of B-byte blocks whose pointers are all
+// aligned to min_align bytes.
+LaunchCfg default_cfg(Mode mode, uint64_t B, int min_align, int num_cu);
+// hipError_t -> RS_OK / RS_EDEVICE.
+int hip_status(int err);
+
+// Checks flags and an erasure list against the code; on success writes the
+// list sorted increasingly to sorted_out (capacity kMaxM).
+int validate_erasures(const Code &c, const int *e, int t, unsigned flags, int *sorted_out);
+
+void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *const *parity,
+                        uint64_t B, CodecParams *p);
+void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
+                        const int *sorted, int t, uint64_t B, CodecParams *p);
+
+}  // namespace rsp

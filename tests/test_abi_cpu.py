@@ -1,0 +1,161 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, validates its arguments before touching the device, and its host-side
+decode plan (the per-pattern coefficients) rebuilds erased blocks when
+applied on the CPU to remainders computed by the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_1312_5155_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(rs_[a-z_0-9]+)\s*\(",
+                            text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = declared_functions()
+    assert "rs_poly_init" in names and "rs_poly_decode" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("k,m,w,poly,err", [
+    (0, 4, 8, 0x11D, B.RS_EINVAL),
+    (10, 0, 8, 0x11D, B.RS_EINVAL),
+    (10, 9, 8, 0x11D, B.RS_EINVAL),       # m above RS_POLY_MAX_M
+    (250, 6, 8, 0x11D, B.RS_EINVAL),      # n = 256 > 2^8 - 1
+    (12, 4, 4, 0x13, B.RS_EINVAL),        # n = 16 > 2^4 - 1
+    (10, 4, 6, 0x43, B.RS_EINVAL),        # w not in {4, 8}
+    (10, 4, 8, 0x11B, B.RS_EINVAL),       # irreducible, x not primitive
+    (10, 4, 8, 0x1D, B.RS_EINVAL),        # degree != w
+    (10, 4, 4, 0x11D, B.RS_EINVAL),
+])
+def test_init_rejects(k, m, w, poly, err):
+    h = ctypes.c_void_p()
+    assert B.load().rs_poly_init(k, m, w, poly, ctypes.byref(h)) == err
+    assert not h.value
+
+
+def test_init_null_out():
+    assert B.load().rs_poly_init(10, 4, 8, 0x11D, None) == B.RS_ENULL
+
+
+def test_strerror_covers_codes():
+    for c in range(0, -8, -1):
+        assert B.rs_poly_strerror(c) != "unknown status"
+    assert B.rs_poly_strerror(-99) == "unknown status"
+
+
+def test_generator_matches_paper_and_oracle(golden_example):
+    code = B.Code(4, 3)
+    assert code.generator() == golden_example["genpoly_m3"]   # Sec. 3.1
+    F = oracle.Field(8, 0x11D)
+    for m in range(1, 9):
+        assert B.Code(10, m).generator() == oracle.genpoly(F, m).tolist()
+    F4 = oracle.Field(4, 0x13)
+    assert B.Code(4, 3, 4, 0x13).generator() == oracle.genpoly(F4, 3).tolist()
+
+
+def test_validation_happens_before_any_device_call():
+    # These return errors (or no-op success) without a GPU in the container.
+    lib = B.load()
+    code = B.Code(10, 4)
+    h = code.handle
+    ptrs = (ctypes.c_void_p * 14)(*([0x1000] * 14))
+    def dec(er, flags=0, blocks=ptrs, nbytes=4096):
+        arr = (ctypes.c_int * max(1, len(er)))(*er)
+        return lib.rs_poly_decode(h, blocks, nbytes, arr, len(er), flags, None)
+    assert dec([0, 1, 2, 3, 4]) == B.RS_ETOOMANY
+    assert dec([0, 0]) == B.RS_ERANGE
+    assert dec([14]) == B.RS_ERANGE
+    assert dec([-1]) == B.RS_ERANGE
+    assert dec([1], flags=2) == B.RS_EINVAL
+    assert dec([]) == B.RS_OK                      # t = 0: no-op
+    assert dec([3], blocks=None) == B.RS_ENULL
+    assert lib.rs_poly_decode(h, ptrs, 4096, None, 2, 0, None) == B.RS_ENULL
+    assert lib.rs_poly_decode(None, ptrs, 4096, None, 0, 0, None) == B.RS_ENULL
+    assert lib.rs_poly_decode(h, ptrs, 4096, None, -1, 0, None) == B.RS_EINVAL
+    # an erased block's pointer is required; an unread survivor's is not
+    holes = (ctypes.c_void_p * 14)(*([0x1000] * 14))
+    holes[5] = None
+    assert dec([5], blocks=holes) == B.RS_ENULL
+    holes2 = (ctypes.c_void_p * 14)(*([0x1000] * 14))
+    holes2[13] = None       # parity p3, unread when only data block 2 is lost
+    assert dec([2], blocks=holes2, nbytes=0) == B.RS_OK
+    assert dec([2], blocks=holes2, flags=B.RS_POLY_FLAG_ALL_SURVIVORS, nbytes=0) == B.RS_ENULL
+    d = (ctypes.c_void_p * 10)(*([0x1000] * 10))
+    p = (ctypes.c_void_p * 4)(*([0x2000] * 4))
+    assert lib.rs_poly_encode(h, d, p, 0, None) == B.RS_OK   # empty: no-op
+    assert lib.rs_poly_encode(h, None, p, 16, None) == B.RS_ENULL
+    p[2] = None
+    assert lib.rs_poly_encode(h, d, p, 16, None) == B.RS_ENULL
+
+
+def apply_plan_on_cpu(F, k, m, full, erasures, flags, code):
+    """Rebuilds the erased rows of `full` with the library's plan: remainder
+    of the received word (unread and erased rows zeroed) by the oracle, then
+    lost_e = sum_l C[e][l] r_l with the oracle's product table."""
+    read, C = code.decode_plan(erasures, flags)
+    recv = np.zeros_like(full)
+    recv[read] = full[read]
+    r = oracle.encode(F, k, m, recv[:k]) ^ recv[k:]
+    mul = F.mul_table()
+    out = {}
+    for e, row in zip(erasures, C):
+        acc = np.zeros(full.shape[1], dtype=np.uint8)
+        for l in range(m):
+            acc ^= mul[row[l], r[l]]
+        out[e] = acc
+    return read, out
+
+
+@pytest.mark.parametrize("flags", [0, B.RS_POLY_FLAG_ALL_SURVIVORS])
+def test_decode_plan_every_pattern_rs63(flags):
+    F = oracle.Field(8, 0x11D)
+    k, m = 6, 3
+    code = B.Code(k, m)
+    data = workloads.random_bytes(21, (k, 257))
+    full = np.concatenate([data, oracle.encode(F, k, m, data)])
+    for er in workloads.all_patterns(k + m, m)[1:]:
+        er = list(reversed(er))
+        read, out = apply_plan_on_cpu(F, k, m, full, er, flags, code)
+        assert read == sorted(read) and not set(read) & set(er)
+        assert len(read) == (k + m - len(er) if flags else k)
+        for e, v in out.items():
+            assert np.array_equal(v, full[e]), (er, e)
+
+
+@pytest.mark.parametrize("k,m,w,poly", [(10, 4, 8, 0x11D), (12, 4, 8, 0x11D),
+                                        (32, 8, 8, 0x11D), (5, 7, 8, 0x11D),
+                                        (4, 3, 4, 0x13), (9, 5, 4, 0x19)])
+def test_decode_plan_random_patterns(k, m, w, poly):
+    F = oracle.Field(w, poly)
+    code = B.Code(k, m, w, poly)
+    rng = workloads.meta_rng(k * 1000 + m)
+    data = workloads.random_bytes(k + m, (k, 300)) & ((1 << w) - 1)
+    full = np.concatenate([data, oracle.encode(F, k, m, data)])
+    for _ in range(40):
+        t = int(rng.integers(1, m + 1))
+        er = workloads.random_erasures(rng, k + m, t)
+        for flags in (0, B.RS_POLY_FLAG_ALL_SURVIVORS):
+            _, out = apply_plan_on_cpu(F, k, m, full, er, flags, code)
+            for e, v in out.items():
+                assert np.array_equal(v, full[e]), (er, e, flags)
