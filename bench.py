@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Throughput of batched polynomial RS encode + erasure decode on one MI355X.
+
+Workload (the headline configuration): RS(10,4) over GF(2^8) (field
+polynomial 0x11D, roots alpha^0..alpha^3), 256 stripes x 10 data blocks x
+1 MiB of uniform random bytes (2.5 GiB of data) resident in HBM.  One step =
+one batched encode of all 256 stripes + one batched decode of all 256
+stripes, each with 1-4 uniformly random erased blocks (one persistent,
+graph-replayed launch each).  `value` is user data per second: k * B bytes
+per stripe, counted once for the encode and once for the decode.
+
+Also reported: the plain one-launch-per-stripe path on the same buffers, the
+dominant kernel against the HBM roofline (algorithmic bytes per launch /
+launch time from HIP events on the launch stream), and the CPU oracle timed
+on a bounded sample of the same stripes on this host.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RS-poly encode/decode GB/s user data (% HBM peak), batched vs plain; p99 latency"
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+K, M, STRIPES, BLOCK = 10, 4, 256, 1 << 20
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("codec.hip", "rs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1312_5155_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, src_hash):
+    """HBM bytes per launch from the committed counter summary, or None if
+    it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_rs104_256x1MiB.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != src_hash:
+        return None
+    return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(host_stripes, erasures, threads):
+    """The oracle, unchanged, on a bounded sample: encode then decode of each
+    sampled stripe; stripes run in parallel threads (ctypes drops the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    F = oracle.Field(8, 0x11D)
+
+    def one(i):
+        data = host_stripes[i]
+        par = oracle.encode(F, K, M, data)
+        full = np.concatenate([data, par])
+        full[erasures[i]] = 0
+        oracle.decode(F, K, M, full, erasures[i])
+        return full
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(len(host_stripes))))
+    dt = time.perf_counter() - t0
+    user = 2 * len(host_stripes) * K * BLOCK
+    return user / dt / 1e9, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=48,
+                    help="stripes the CPU oracle encodes+decodes (0 = skip)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on this workload before timing")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(stripes shard across GPUs with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_1312_5155_amd import binding as B
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    # Stripes resident in HBM: (stripe, block, byte).
+    buf = torch.empty((STRIPES, K + M, BLOCK), dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(workloads.data_seed(1))
+    for s in range(STRIPES):
+        buf[s, :K] = torch.randint(0, 256, (K, BLOCK), dtype=torch.uint8, device=dev,
+                                   generator=gen)
+    rng = workloads.meta_rng(workloads.meta_seed(1))
+    erasures = []
+    for s in range(STRIPES):
+        t = int(rng.integers(1, M + 1))
+        erasures.append(workloads.random_erasures(rng, K + M, t))
+
+    code = B.Code(K, M)
+    ptrs = [[buf[s, b].data_ptr() for b in range(K + M)] for s in range(STRIPES)]
+    enc = B.StripeArray([(code, ptrs[s], BLOCK) for s in range(STRIPES)])
+    dec = B.StripeArray([(code, ptrs[s], BLOCK, erasures[s], 0) for s in range(STRIPES)])
+    batch = B.Batch()
+    if args.tune:
+        batch.tune(B.RS_POLY_OP_ENCODE, enc, stream)
+        batch.tune(B.RS_POLY_OP_DECODE, dec, stream)
+
+    def step():
+        batch.encode(enc, stream)
+        batch.decode(dec, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        batch.encode(enc, stream)
+        ev[i][1].record(stream)
+        batch.decode(dec, stream)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    enc_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    dec_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+
+    user_per_op = STRIPES * K * BLOCK
+    enc_alg = STRIPES * (K + M) * BLOCK                          # read k, write m
+    dec_alg = sum((K + len(e)) * BLOCK for e in erasures)         # read k, write t
+    value = 2 * user_per_op / (ms_per_step / 1e3) / 1e9
+
+    # Plain: one launch per stripe, same buffers and patterns.
+    def plain_step():
+        for s in range(STRIPES):
+            B.rs_poly_encode(code.handle, ptrs[s][:K], ptrs[s][K:], BLOCK, stream)
+        for s in range(STRIPES):
+            B.rs_poly_decode(code.handle, ptrs[s], BLOCK, erasures[s], 0, stream)
+
+    plain = None
+    if args.plain_steps > 0:
+        plain_step()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+        plain = {"ms_per_step": round(plain_ms, 4),
+                 "value": round(2 * user_per_op / (plain_ms / 1e3) / 1e9, 1),
+                 "launches_per_step": 2 * STRIPES}
+
+    # The output must still be a valid codeword set: spot-check stripe 0.
+    import numpy as np
+
+    import oracle
+    F = oracle.Field(8, 0x11D)
+    host0 = buf[0].cpu().numpy()
+    assert np.array_equal(oracle.encode(F, K, M, host0[:K]), host0[K:]), "parity check failed"
+
+    src_hash = kernel_source_hash()
+    kernels = {
+        "batch_encode": {"avg_ms": round(enc_ms, 4), "alg_bytes": enc_alg,
+                         "gbs": round(enc_alg / (enc_ms / 1e3) / 1e9, 1)},
+        "batch_decode": {"avg_ms": round(dec_ms, 4), "alg_bytes": dec_alg,
+                         "gbs": round(dec_alg / (dec_ms / 1e3) / 1e9, 1)},
+    }
+    dom = "batch_encode" if enc_ms >= dec_ms else "batch_decode"
+    achieved = kernels[dom]["gbs"]
+    traffic = measured_traffic(dom, src_hash)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        n = min(args.cpu_sample, STRIPES)
+        host = [buf[s, :K].cpu().numpy() for s in range(n)]
+        threads = min(16, os.cpu_count() or 1)
+        gbs, secs = cpu_baseline(host, erasures[:n], threads)
+        cpu = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+               "sample": f"{n} of the {STRIPES} stripes, encode + decode each "
+                         f"({secs:.1f} s wall on {threads} threads)"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "rs104_256x1MiB",
+                   "code": "RS(10,4) GF(2^8) poly 0x11D roots alpha^0..alpha^3",
+                   "stripes": STRIPES, "block_bytes": BLOCK,
+                   "step": "batched encode + batched decode, 1-4 random erasures per stripe"},
+        "hbm_frac": round((enc_alg + dec_alg) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": kernels,
+        "launch": {"encode": batch.get_launch(B.RS_POLY_OP_ENCODE, 0).as_dict(),
+                   "decode": batch.get_launch(B.RS_POLY_OP_DECODE, 0).as_dict()},
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,7 +82,7 @@ typedef struct rs_poly rs_poly_t;
  *   w          symbol width in bits, 4 or 8
  *   prim_poly  field polynomial with bit w set, e.g. 0x11D (w=8) or 0x13 (w=4);
  *              it must be primitive, i.e. alpha = 2 = x generates the field
- *              (Sec. 3.1 example: "the primitive root is 2")
+ *              (the Sec. 3.1 example takes 2 as the primitive root)
  *   out        receives the handle
  * Errors: RS_ENULL (out), RS_EINVAL (k, m, w or prim_poly, or k+m > 2^w - 1:
  * the n positions alpha^pos must be distinct), RS_ENOMEM. */
@@ -139,6 +139,89 @@ int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
 int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures,
                         unsigned flags, int *read_set, int *n_read,
                         uint8_t *coeffs);
+
+/* ------------------------------------------------------------ batches --
+ *
+ * Many stripes -- uneven block sizes, different codes -- go through ONE
+ * persistent kernel launch per state width (codes with m <= 4, and codes
+ * with 4 < m <= 8), replayed from a hipGraph captured once per batch object
+ * and launch shape.  The columns of all stripes are cut into tiles that
+ * persistent workgroups take from a device-side counter.  Arithmetic and
+ * results are exactly those of rs_poly_encode / rs_poly_decode on each
+ * stripe (Sec. 3.2 and 3.3); only the launch is shared.  Batching is not in
+ * the paper; it is how the GPU is kept full with stripes of any size. */
+
+/* One stripe of a batch call. */
+typedef struct rs_poly_stripe {
+    rs_poly_t *code;             /* its code handle                          */
+    uint8_t *const *blocks;      /* host array of n = k+m device pointers,   *
+                                  * API block order (encode: reads 0..k-1,   *
+                                  * writes k..n-1)                           */
+    size_t block_bytes;          /* bytes per block; 0 = nothing to do       */
+    const int *erasures;         /* decode only: lost API indices            */
+    int n_erasures;              /* decode only: t, 0 <= t <= m              */
+    unsigned flags;              /* decode only: 0 or RS_POLY_FLAG_ALL_SURVIVORS */
+} rs_poly_stripe_t;
+
+/* Launch shape of a batch kernel (what the autotuner chooses). */
+typedef struct rs_poly_launch {
+    int bytes_per_lane;   /* columns per lane per block: 4, 8 or 16            */
+    int threads;          /* workgroup size: 256, 512 or 1024; at 16 bytes per *
+                           * lane at most 512 (m <= 4) or 256 (m > 4)          */
+    int tile_bytes;       /* columns per tile: a multiple of 16, >= 4096       */
+    int wgs_per_cu;       /* persistent workgroups per CU: 1 or 2              */
+} rs_poly_launch_t;
+
+#define RS_POLY_OP_ENCODE 0
+#define RS_POLY_OP_DECODE 1
+
+typedef struct rs_poly_batch rs_poly_batch_t;
+
+/* Creates a batch object: device descriptor buffers, pinned staging and
+ * captured graphs, all grown on demand and owned by the object.  Binds to
+ * the device current at creation; calls must be made with that device
+ * current.  Errors: RS_ENULL, RS_ENOMEM, RS_EDEVICE. */
+int rs_poly_batch_create(rs_poly_batch_t **out);
+
+/* Waits for the object's own pending uploads, then frees it.  The caller
+ * must not free it with its kernels still queued.  NULL is a no-op. */
+void rs_poly_batch_free(rs_poly_batch_t *b);
+
+/* Encodes every stripe (parity of Sec. 3.2, eq. (1)-(2)) with one graph
+ * launch per state width on `stream`.  Every block pointer must be 16-byte
+ * aligned (else RS_EINVAL; rs_poly_encode takes any alignment).  Outputs of
+ * different stripes must not overlap.  The stripe array and the host arrays
+ * it points to are read during the call only.
+ * Errors: RS_ENULL, RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
+int rs_poly_batch_encode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
+                         int count, void *stream);
+
+/* Erasure-decodes every stripe (Sec. 3.3), as rs_poly_decode would, with one
+ * graph launch per state width.  Per-stripe erasure lists are validated as
+ * in rs_poly_decode; any error rejects the whole call before any work.
+ * Errors: RS_ENULL, RS_EINVAL, RS_ERANGE, RS_ETOOMANY, RS_ENOMEM,
+ * RS_EDEVICE. */
+int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
+                         int count, void *stream);
+
+/* Reads or sets the launch shape used for (op, state width), where wide = 0
+ * selects codes with m <= 4 and wide = 1 codes with 4 < m <= 8.  Shapes are
+ * validated (RS_EINVAL). */
+int rs_poly_batch_get_launch(const rs_poly_batch_t *b, int op, int wide,
+                             rs_poly_launch_t *cfg);
+int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide,
+                             const rs_poly_launch_t *cfg);
+
+/* Autotuner: times every candidate launch shape on these stripes (running
+ * the real operation, which is idempotent, several times on `stream`),
+ * keeps the fastest for each state width present, and returns the shape
+ * chosen for the width carrying the most bytes in *best (may be NULL).
+ * Blocks until the timing runs finish.  If the environment variable
+ * RS_POLY_TUNE_CACHE names a file, results are read from / appended to it
+ * as JSON lines keyed by device architecture, op, width and block-size
+ * bucket, and a cached entry skips the timing. */
+int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes,
+                 int count, void *stream, rs_poly_launch_t *best);
 
 #ifdef __cplusplus
 }

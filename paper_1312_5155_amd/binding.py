@@ -55,8 +55,41 @@ def load():
     lib.rs_poly_encode.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_decode.argtypes = [vp, pp, sz, ip, i, u, vp]
     lib.rs_poly_decode_plan.argtypes = [vp, ip, i, u, ip, ip, u8p]
+    sp = ctypes.POINTER(Stripe)
+    lp = ctypes.POINTER(Launch)
+    lib.rs_poly_batch_create.argtypes = [ctypes.POINTER(vp)]
+    lib.rs_poly_batch_free.argtypes = [vp]
+    lib.rs_poly_batch_free.restype = None
+    lib.rs_poly_batch_encode.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_batch_decode.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_batch_get_launch.argtypes = [vp, i, i, lp]
+    lib.rs_poly_batch_set_launch.argtypes = [vp, i, i, lp]
+    lib.rs_poly_tune.argtypes = [vp, i, sp, i, vp, lp]
     _lib = lib
     return lib
+
+
+class Stripe(ctypes.Structure):
+    """rs_poly_stripe_t."""
+    _fields_ = [("code", ctypes.c_void_p),
+                ("blocks", ctypes.POINTER(ctypes.c_void_p)),
+                ("block_bytes", ctypes.c_size_t),
+                ("erasures", ctypes.POINTER(ctypes.c_int)),
+                ("n_erasures", ctypes.c_int),
+                ("flags", ctypes.c_uint)]
+
+
+class Launch(ctypes.Structure):
+    """rs_poly_launch_t."""
+    _fields_ = [("bytes_per_lane", ctypes.c_int), ("threads", ctypes.c_int),
+                ("tile_bytes", ctypes.c_int), ("wgs_per_cu", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+RS_POLY_OP_ENCODE = 0
+RS_POLY_OP_DECODE = 1
 
 
 def check(rc, where):
@@ -137,6 +170,76 @@ def rs_poly_decode_plan(h, n, m, erasures, flags=0):
     return list(rs[:nr.value]), [list(co[r * m:(r + 1) * m]) for r in range(t)]
 
 
+class StripeArray:
+    """A prepared rs_poly_stripe_t array (and the host arrays it points to),
+    reusable across batch calls.  Entries: (code, blocks, block_bytes) for
+    encode, plus (erasures, flags) for decode."""
+
+    def __init__(self, entries):
+        self.count = len(entries)
+        self.arr = (Stripe * max(1, self.count))()
+        self._keep = []
+        for i, e in enumerate(entries):
+            code, blocks, nbytes = e[0], e[1], e[2]
+            er = list(e[3]) if len(e) > 3 and e[3] is not None else []
+            flags = e[4] if len(e) > 4 else 0
+            bl = _ptr_array(list(blocks))
+            ea = (ctypes.c_int * max(1, len(er)))(*er)
+            self._keep += [bl, ea]
+            h = code.handle if isinstance(code, Code) else code
+            self.arr[i] = Stripe(h, ctypes.cast(bl, ctypes.POINTER(ctypes.c_void_p)),
+                                 nbytes, ctypes.cast(ea, ctypes.POINTER(ctypes.c_int)),
+                                 len(er), flags)
+
+
+def rs_poly_batch_create():
+    b = ctypes.c_void_p()
+    check(load().rs_poly_batch_create(ctypes.byref(b)), "rs_poly_batch_create")
+    return b
+
+
+def rs_poly_batch_free(b):
+    load().rs_poly_batch_free(b)
+
+
+def _stripes(stripes):
+    return stripes if isinstance(stripes, StripeArray) else StripeArray(stripes)
+
+
+def rs_poly_batch_encode(b, stripes, stream=None):
+    sa = _stripes(stripes)
+    return check(load().rs_poly_batch_encode(b, sa.arr, sa.count, _stream(stream)),
+                 "rs_poly_batch_encode")
+
+
+def rs_poly_batch_decode(b, stripes, stream=None):
+    sa = _stripes(stripes)
+    return check(load().rs_poly_batch_decode(b, sa.arr, sa.count, _stream(stream)),
+                 "rs_poly_batch_decode")
+
+
+def rs_poly_batch_get_launch(b, op, wide):
+    c = Launch()
+    check(load().rs_poly_batch_get_launch(b, op, wide, ctypes.byref(c)),
+          "rs_poly_batch_get_launch")
+    return c
+
+
+def rs_poly_batch_set_launch(b, op, wide, cfg):
+    if isinstance(cfg, dict):
+        cfg = Launch(**cfg)
+    return check(load().rs_poly_batch_set_launch(b, op, wide, ctypes.byref(cfg)),
+                 "rs_poly_batch_set_launch")
+
+
+def rs_poly_tune(b, op, stripes, stream=None):
+    sa = _stripes(stripes)
+    best = Launch()
+    check(load().rs_poly_tune(b, op, sa.arr, sa.count, _stream(stream), ctypes.byref(best)),
+          "rs_poly_tune")
+    return best
+
+
 # ------------------------------------------------------ convenience --
 
 class Code:
@@ -177,3 +280,40 @@ class Code:
 
     def decode_plan(self, erasures, flags=0):
         return rs_poly_decode_plan(self._h, self.n, self.m, list(erasures), flags)
+
+
+class Batch:
+    """A batch object: one persistent, graph-replayed launch per call."""
+
+    def __init__(self):
+        self._b = rs_poly_batch_create()
+
+    @property
+    def handle(self):
+        return self._b
+
+    def close(self):
+        if self._b is not None:
+            rs_poly_batch_free(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def encode(self, stripes, stream=None):
+        return rs_poly_batch_encode(self._b, stripes, stream)
+
+    def decode(self, stripes, stream=None):
+        return rs_poly_batch_decode(self._b, stripes, stream)
+
+    def get_launch(self, op, wide=0):
+        return rs_poly_batch_get_launch(self._b, op, wide)
+
+    def set_launch(self, op, wide, cfg):
+        return rs_poly_batch_set_launch(self._b, op, wide, cfg)
+
+    def tune(self, op, stripes, stream=None):
+        return rs_poly_tune(self._b, op, stripes, stream)

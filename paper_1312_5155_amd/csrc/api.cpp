@@ -13,11 +13,6 @@
 #include "rs_internal.h"
 #include "runtime.h"
 
-struct rs_poly {
-  rsp::Code code;
-  std::mutex mu;
-};
-
 namespace rsp {
 
 int device_cu_count() {
@@ -36,6 +31,24 @@ int device_cu_count() {
   return cache[dev];
 }
 
+const uint8_t *device_zero_page() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  static std::mutex mu;
+  static uint8_t *pages[64] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pages[dev]) {
+    void *p = nullptr;
+    if (hipMalloc(&p, kZeroPageBytes) != hipSuccess) return nullptr;
+    if (hipMemset(p, 0, kZeroPageBytes) != hipSuccess) {
+      (void)hipFree(p);
+      return nullptr;
+    }
+    pages[dev] = static_cast<uint8_t *>(p);
+  }
+  return pages[dev];
+}
+
 int pointer_alignment(const void *p) {
   const uintptr_t v = reinterpret_cast<uintptr_t>(p);
   if ((v & 15) == 0) return 16;
@@ -44,19 +57,19 @@ int pointer_alignment(const void *p) {
   return 1;
 }
 
-LaunchCfg default_cfg(Mode mode, uint64_t B, int min_align, int num_cu) {
+LaunchCfg default_cfg(Mode mode, int sb, uint64_t B, int min_align, int num_cu) {
   LaunchCfg cfg{};
-  cfg.threads = mode == kDecode ? 1024 : 512;
   if (min_align < 4) {
     cfg.bytewise = true;
     cfg.dwords_per_lane = 1;
   } else {
     // Widest loads that still give every CU a few thousand lanes of work.
     const uint64_t want_lanes = (uint64_t)num_cu * 1024;
-    int w = std::min(4, min_align / 4);
+    int w = std::min(codec_plain_max_dwords(sb), min_align / 4);
     while (w > 1 && (B + 4 * w - 1) / (4 * w) < want_lanes) w /= 2;
     cfg.dwords_per_lane = w;
   }
+  cfg.threads = std::min(512, codec_max_threads(sb, cfg.dwords_per_lane));
   const uint64_t cols = 4ull * cfg.dwords_per_lane;
   const uint64_t chunks = (B + cols - 1) / cols;
   const uint64_t wgs = (chunks + cfg.threads - 1) / cfg.threads;
@@ -85,9 +98,9 @@ int validate_erasures(const Code &c, const int *e, int t, unsigned flags, int *s
 static int round_up(int x, int to) { return (x + to - 1) / to * to; }
 
 void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *const *parity,
-                        uint64_t B, CodecParams *p) {
-  for (int j = 0; j < c.k(); ++j) p->data[j] = data[j];
-  for (int i = 0; i < c.m(); ++i) p->out[i] = parity[i];
+                        uint64_t offset, uint64_t B, CodecParams *p) {
+  for (int j = 0; j < c.k(); ++j) p->data[j] = data[j] + offset;
+  for (int i = 0; i < c.m(); ++i) p->out[i] = parity[i] + offset;
   p->block_bytes = B;
   p->k = c.k();
   p->m = c.m();
@@ -97,14 +110,15 @@ void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *cons
 }
 
 void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
-                        const int *sorted, int t, uint64_t B, CodecParams *p) {
+                        const int *sorted, int t, uint64_t offset, uint64_t B,
+                        CodecParams *p) {
   for (int b : plan.read) {
     if (b < c.k())
-      p->data[b] = blocks[b];
+      p->data[b] = blocks[b] + offset;
     else
-      p->par_in[b - c.k()] = blocks[b];
+      p->par_in[b - c.k()] = blocks[b] + offset;
   }
-  for (int r = 0; r < t; ++r) p->out[r] = blocks[sorted[r]];
+  for (int r = 0; r < t; ++r) p->out[r] = blocks[sorted[r]] + offset;
   p->block_bytes = B;
   p->k = c.k();
   p->m = c.m();
@@ -171,14 +185,22 @@ int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data, uint8_t *const *par
   }
   if (block_bytes == 0) return RS_OK;
 
-  CodecParams p;
-  memset(&p, 0, sizeof(p));
-  fill_encode_params(c, data, parity, block_bytes, &p);
   std::lock_guard<std::mutex> lock(h->mu);
   const int ncu = device_cu_count();
-  if (ncu <= 0) return RS_EDEVICE;
-  const LaunchCfg cfg = default_cfg(kEncode, block_bytes, align, ncu);
-  return hip_status(launch_codec(kEncode, c.state_bytes(), p, cfg, stream));
+  const uint8_t *zp = device_zero_page();
+  if (ncu <= 0 || !zp) return RS_EDEVICE;
+  // One launch per column range of at most kMaxPieceBytes.
+  for (uint64_t off = 0; off < block_bytes; off += kMaxPieceBytes) {
+    const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
+    CodecParams p;
+    memset(&p, 0, sizeof(p));
+    fill_encode_params(c, data, parity, off, piece, &p);
+    p.zero_page = zp;
+    const LaunchCfg cfg = default_cfg(kEncode, c.state_bytes(), piece, align, ncu);
+    const int rc = hip_status(launch_codec(kEncode, c.state_bytes(), p, cfg, stream));
+    if (rc != RS_OK) return rc;
+  }
+  return RS_OK;
 }
 
 int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
@@ -201,14 +223,22 @@ int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
   }
   if (block_bytes == 0) return RS_OK;
 
-  CodecParams p;
-  memset(&p, 0, sizeof(p));
-  fill_decode_params(h->code, *plan, blocks, sorted, n_erasures, block_bytes, &p);
   std::lock_guard<std::mutex> lock(h->mu);
   const int ncu = device_cu_count();
-  if (ncu <= 0) return RS_EDEVICE;
-  const LaunchCfg cfg = default_cfg(kDecode, block_bytes, align, ncu);
-  return hip_status(launch_codec(kDecode, h->code.state_bytes(), p, cfg, stream));
+  const uint8_t *zp = device_zero_page();
+  if (ncu <= 0 || !zp) return RS_EDEVICE;
+  const int sb = h->code.state_bytes();
+  for (uint64_t off = 0; off < block_bytes; off += kMaxPieceBytes) {
+    const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
+    CodecParams p;
+    memset(&p, 0, sizeof(p));
+    fill_decode_params(h->code, *plan, blocks, sorted, n_erasures, off, piece, &p);
+    p.zero_page = zp;
+    const LaunchCfg cfg = default_cfg(kDecode, sb, piece, align, ncu);
+    const int rc = hip_status(launch_codec(kDecode, sb, p, cfg, stream));
+    if (rc != RS_OK) return rc;
+  }
+  return RS_OK;
 }
 
 int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures, unsigned flags,

@@ -1,0 +1,583 @@
+// Batched encode/decode: stripe descriptors, pinned staging, graph capture
+// and replay, and the launch-shape autotuner with its cache file.
+#include <hip/hip_runtime_api.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/rs_poly.h"
+#include "gf.h"
+#include "rs_internal.h"
+#include "runtime.h"
+
+namespace rsp {
+namespace {
+
+constexpr int kOps = 2;     // encode, decode
+constexpr int kWidths = 2;  // state width 4 bytes (m <= 4), 8 bytes (m <= 8)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct GroupBuf {
+  uint8_t *arena = nullptr;       // device: header + packed regions
+  size_t arena_bytes = 0;
+  uint32_t *tile_stripe = nullptr;
+  uint64_t tile_cap = 0;
+  uint32_t stripe_cap = 0;        // bounds the prepare-kernel grid
+  uint64_t version = 0;           // bumped when device buffers move
+};
+
+using GraphKey = std::tuple<int, int, int, int, int, int, uint64_t>;
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
+  if (c.bytes_per_lane != 4 && c.bytes_per_lane != 8 && c.bytes_per_lane != 16) return false;
+  if (c.threads != 256 && c.threads != 512 && c.threads != 1024) return false;
+  if (c.threads > codec_max_threads(wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
+  if (c.tile_bytes < 4096 || c.tile_bytes % 16 != 0) return false;
+  (void)op;
+  return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 2;
+}
+
+// Defaults from a sweep of every shape on RS(10,4), 256 x 1 MiB stripes,
+// MI355X (the autotuner refines them per workload).
+rs_poly_launch_t default_launch(int op, int wide) {
+  rs_poly_launch_t c;
+  if (op == RS_POLY_OP_ENCODE && !wide) {
+    c.bytes_per_lane = 8;
+    c.threads = 1024;
+    c.tile_bytes = 16 << 10;
+  } else {
+    c.bytes_per_lane = 16;
+    c.threads = wide ? 256 : 512;
+    c.tile_bytes = 64 << 10;
+  }
+  c.wgs_per_cu = 2;
+  return c;
+}
+
+}  // namespace
+}  // namespace rsp
+
+using namespace rsp;
+
+struct rs_poly_batch {
+  std::mutex mu;
+  int device = 0;
+  int num_cu = 0;
+  std::string arch;
+  hipStream_t capture = nullptr;
+  GroupBuf groups[kWidths];
+  uint8_t *staging = nullptr;     // pinned host memory, both groups
+  size_t staging_bytes = 0;
+  hipEvent_t staging_free = nullptr;
+  bool staging_pending = false;
+  rs_poly_launch_t launch[kOps][kWidths];
+  std::map<GraphKey, GraphEntry> graphs;
+
+  ~rs_poly_batch();
+  void drop_graphs();
+  int ensure_staging(size_t bytes);
+  int ensure_group(int wide, size_t arena_bytes, uint64_t tiles, uint32_t stripes);
+  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, hipGraphExec_t *out);
+  int run(int op, const rs_poly_stripe_t *stripes, int count, void *stream);
+};
+
+void rs_poly_batch::drop_graphs() {
+  for (auto &kv : graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  graphs.clear();
+}
+
+rs_poly_batch::~rs_poly_batch() {
+  if (staging_pending && staging_free) (void)hipEventSynchronize(staging_free);
+  drop_graphs();
+  for (auto &g : groups) {
+    if (g.arena) (void)hipFree(g.arena);
+    if (g.tile_stripe) (void)hipFree(g.tile_stripe);
+  }
+  if (staging) (void)hipHostFree(staging);
+  if (staging_free) (void)hipEventDestroy(staging_free);
+  if (capture) (void)hipStreamDestroy(capture);
+}
+
+int rs_poly_batch::ensure_staging(size_t bytes) {
+  if (bytes <= staging_bytes) return RS_OK;
+  if (staging_pending) {
+    if (hipEventSynchronize(staging_free) != hipSuccess) return RS_EDEVICE;
+    staging_pending = false;
+  }
+  if (staging) (void)hipHostFree(staging);
+  staging = nullptr;
+  staging_bytes = 0;
+  const size_t want = align_up(bytes + bytes / 2, 1 << 16);
+  if (hipHostMalloc(reinterpret_cast<void **>(&staging), want, hipHostMallocDefault) !=
+      hipSuccess)
+    return RS_ENOMEM;
+  staging_bytes = want;
+  return RS_OK;
+}
+
+int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
+                                uint32_t stripes) {
+  GroupBuf &g = groups[wide];
+  if (arena_bytes <= g.arena_bytes && tiles <= g.tile_cap && stripes <= g.stripe_cap)
+    return RS_OK;
+  // Buffers move: kernels queued earlier may still use them.
+  if (hipDeviceSynchronize() != hipSuccess) return RS_EDEVICE;
+  const size_t new_arena = std::max(g.arena_bytes, align_up(arena_bytes + arena_bytes / 2, 4096));
+  const uint64_t new_tiles = std::max<uint64_t>(g.tile_cap, tiles + tiles / 2 + 64);
+  const uint32_t new_stripes = std::max<uint32_t>(g.stripe_cap, stripes + stripes / 2 + 16);
+  if (g.arena) (void)hipFree(g.arena);
+  if (g.tile_stripe) (void)hipFree(g.tile_stripe);
+  g.arena = nullptr;
+  g.tile_stripe = nullptr;
+  g.arena_bytes = g.tile_cap = g.stripe_cap = 0;
+  if (hipMalloc(reinterpret_cast<void **>(&g.arena), new_arena) != hipSuccess) return RS_ENOMEM;
+  if (hipMalloc(reinterpret_cast<void **>(&g.tile_stripe), new_tiles * sizeof(uint32_t)) !=
+      hipSuccess)
+    return RS_ENOMEM;
+  g.arena_bytes = new_arena;
+  g.tile_cap = new_tiles;
+  g.stripe_cap = new_stripes;
+  ++g.version;
+  // Graphs of this group hold the old pointers.
+  for (auto it = graphs.begin(); it != graphs.end();) {
+    if (std::get<1>(it->first) == wide) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      (void)hipGraphDestroy(it->second.graph);
+      it = graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return RS_OK;
+}
+
+int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
+                             hipGraphExec_t *out) {
+  GroupBuf &gb = groups[wide];
+  const GraphKey key{op, wide, cfg.bytes_per_lane, cfg.threads, cfg.tile_bytes, cfg.wgs_per_cu,
+                     gb.version};
+  auto it = graphs.find(key);
+  if (it != graphs.end()) {
+    *out = it->second.exec;
+    return RS_OK;
+  }
+  const uint8_t *zp = device_zero_page();
+  if (!zp) return RS_EDEVICE;
+  BatchGroup g{gb.arena, gb.tile_stripe, zp, (uint32_t)cfg.tile_bytes};
+  LaunchCfg lc{};
+  lc.dwords_per_lane = cfg.bytes_per_lane / 4;
+  lc.threads = cfg.threads;
+  lc.grid = num_cu * cfg.wgs_per_cu;
+  lc.bytewise = false;
+  GraphEntry e;
+  if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return RS_EDEVICE;
+  const int lerr = launch_batch(op == RS_POLY_OP_DECODE ? kDecode : kEncode, wide ? 8 : 4, g,
+                                gb.stripe_cap, lc, capture);
+  const hipError_t cerr = hipStreamEndCapture(capture, &e.graph);
+  if (lerr != 0 || cerr != hipSuccess) {
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    return RS_EDEVICE;
+  }
+  if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(e.graph);
+    return RS_EDEVICE;
+  }
+  graphs[key] = e;
+  *out = e.exec;
+  return RS_OK;
+}
+
+namespace rsp {
+namespace {
+
+// Per-call host view of one group before upload.
+struct GroupPlan {
+  std::vector<StripeDesc> descs;
+  std::vector<uint64_t> ptrs;
+  std::vector<uint32_t> lfsr;   // 16 per set
+  std::vector<uint32_t> apply;  // kMaxM*16 per set
+  std::unordered_map<const Code *, uint32_t> lfsr_index;
+  std::unordered_map<const DecodePlan *, uint32_t> apply_index;
+  std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
+  uint64_t tiles = 0;
+  uint64_t bytes = 0;   // user bytes (k * B summed), for tuning choices
+
+  size_t layout(size_t *o_descs, size_t *o_ptrs, size_t *o_lfsr, size_t *o_apply) const {
+    size_t off = align_up(sizeof(BatchHeader), 256);
+    *o_descs = off;
+    off = align_up(off + descs.size() * sizeof(StripeDesc), 256);
+    *o_ptrs = off;
+    off = align_up(off + ptrs.size() * sizeof(uint64_t), 256);
+    *o_lfsr = off;
+    off = align_up(off + lfsr.size() * sizeof(uint32_t), 256);
+    *o_apply = off;
+    off = align_up(off + apply.size() * sizeof(uint32_t), 256);
+    return off;
+  }
+};
+
+int check_stripe(int op, const rs_poly_stripe_t &st, int *sorted,
+                 std::shared_ptr<const DecodePlan> *plan) {
+  if (!st.code || !st.blocks) return RS_ENULL;
+  Code &c = st.code->code;
+  const int k = c.k(), m = c.m();
+  auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (op == RS_POLY_OP_ENCODE) {
+    for (int b = 0; b < k + m; ++b) {
+      if (!st.blocks[b]) return RS_ENULL;
+      if (!aligned(st.blocks[b])) return RS_EINVAL;
+    }
+    return RS_OK;
+  }
+  const int rc = validate_erasures(c, st.erasures, st.n_erasures, st.flags, sorted);
+  if (rc != RS_OK) return rc;
+  if (st.n_erasures == 0) return RS_OK;
+  *plan = c.plan(sorted, st.n_erasures, st.flags);
+  for (int b : (*plan)->read) {
+    if (!st.blocks[b]) return RS_ENULL;
+    if (!aligned(st.blocks[b])) return RS_EINVAL;
+  }
+  for (int i = 0; i < st.n_erasures; ++i) {
+    if (!st.blocks[sorted[i]]) return RS_ENULL;
+    if (!aligned(st.blocks[sorted[i]])) return RS_EINVAL;
+  }
+  return RS_OK;
+}
+
+}  // namespace
+}  // namespace rsp
+
+int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void *stream) {
+  if (count < 0) return RS_EINVAL;
+  if (count > 0 && !stripes) return RS_ENULL;
+  GroupPlan plan[kWidths];
+
+  // Validate everything first; build the per-group host layout.
+  for (int i = 0; i < count; ++i) {
+    const rs_poly_stripe_t &st = stripes[i];
+    int sorted[kMaxM];
+    std::shared_ptr<const DecodePlan> dp;
+    const int rc = check_stripe(op, st, sorted, &dp);
+    if (rc != RS_OK) return rc;
+    if (st.block_bytes == 0 || (op == RS_POLY_OP_DECODE && st.n_erasures == 0)) continue;
+    const Code &c = st.code->code;
+    const int wide = c.state_bytes() == 8;
+    GroupPlan &gp = plan[wide];
+    const int k = c.k(), m = c.m();
+
+    uint32_t lset;
+    auto li = gp.lfsr_index.find(&c);
+    if (li == gp.lfsr_index.end()) {
+      li = gp.lfsr_index.emplace(&c, (uint32_t)(gp.lfsr.size() / 16)).first;
+      gp.lfsr.insert(gp.lfsr.end(), c.lfsr_basis(), c.lfsr_basis() + 16);
+    }
+    lset = li->second;
+    uint32_t aset = 0;
+    if (op == RS_POLY_OP_DECODE) {
+      auto ai = gp.apply_index.find(dp.get());
+      if (ai == gp.apply_index.end()) {
+        ai = gp.apply_index.emplace(dp.get(), (uint32_t)(gp.apply.size() / (kMaxM * 16))).first;
+        const uint32_t *ab = &dp->apply_basis[0][0];
+        gp.apply.insert(gp.apply.end(), ab, ab + kMaxM * 16);
+        gp.keep.push_back(dp);
+      }
+      aset = ai->second;
+    }
+    // Blocks longer than kMaxPieceBytes become several independent column
+    // ranges, each with its own descriptor and offset pointers.
+    for (uint64_t off = 0; off < st.block_bytes; off += kMaxPieceBytes) {
+      StripeDesc d{};
+      d.block_bytes = std::min<uint64_t>(kMaxPieceBytes, st.block_bytes - off);
+      d.k = k;
+      d.m = m;
+      d.k_pad = (k + c.state_bytes() - 1) / c.state_bytes() * c.state_bytes();
+      d.ptr_off = gp.ptrs.size();
+      d.lfsr_set = lset;
+      d.apply_set = aset;
+      auto at = [&](int b) { return reinterpret_cast<uint64_t>(st.blocks[b] + off); };
+      if (op == RS_POLY_OP_ENCODE) {
+        d.n_out = m;
+        for (int j = 0; j < k; ++j) gp.ptrs.push_back(at(j));
+        for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(0);
+        for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
+      } else {
+        const int t = st.n_erasures;
+        d.n_out = t;
+        const size_t base = gp.ptrs.size();
+        gp.ptrs.resize(base + k + m + t, 0);
+        // data d_j at entry j, parity p_i at entry k + i: entry b for block b
+        for (int b : dp->read) gp.ptrs[base + b] = at(b);
+        for (int r = 0; r < t; ++r) gp.ptrs[base + k + m + r] = at(sorted[r]);
+      }
+      gp.descs.push_back(d);
+    }
+    gp.bytes += (uint64_t)k * st.block_bytes;
+  }
+
+  // Tiles per stripe depend on the launch shape of the group.
+  size_t total_upload = 0;
+  size_t upload_at[kWidths] = {0, 0};
+  size_t upload_len[kWidths] = {0, 0};
+  size_t offs[kWidths][4];
+  for (int w = 0; w < kWidths; ++w) {
+    GroupPlan &gp = plan[w];
+    if (gp.descs.empty()) continue;
+    const uint64_t tc = (uint64_t)launch[op][w].tile_bytes;
+    uint64_t t = 0;
+    for (auto &d : gp.descs) {
+      d.tile_begin = t;
+      t += (d.block_bytes + tc - 1) / tc;
+    }
+    gp.tiles = t;
+    upload_len[w] = gp.layout(&offs[w][0], &offs[w][1], &offs[w][2], &offs[w][3]);
+    upload_at[w] = total_upload;
+    total_upload += upload_len[w];
+  }
+  if (total_upload == 0) return RS_OK;
+
+  // Device buffers and pinned staging.
+  for (int w = 0; w < kWidths; ++w) {
+    if (plan[w].descs.empty()) continue;
+    const int rc = ensure_group(w, upload_len[w], plan[w].tiles, (uint32_t)plan[w].descs.size());
+    if (rc != RS_OK) return rc;
+  }
+  int rc = ensure_staging(total_upload);
+  if (rc != RS_OK) return rc;
+  if (staging_pending) {
+    if (hipEventSynchronize(staging_free) != hipSuccess) return RS_EDEVICE;
+    staging_pending = false;
+  }
+
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int w = 0; w < kWidths; ++w) {
+    GroupPlan &gp = plan[w];
+    if (gp.descs.empty()) continue;
+    uint8_t *h = staging + upload_at[w];
+    BatchHeader hdr{};
+    hdr.total_tiles = gp.tiles;
+    hdr.n_stripes = (uint32_t)gp.descs.size();
+    hdr.off_descs = offs[w][0];
+    hdr.off_ptrs = offs[w][1];
+    hdr.off_lfsr = offs[w][2];
+    hdr.off_apply = offs[w][3];
+    memcpy(h, &hdr, sizeof(hdr));
+    memcpy(h + offs[w][0], gp.descs.data(), gp.descs.size() * sizeof(StripeDesc));
+    memcpy(h + offs[w][1], gp.ptrs.data(), gp.ptrs.size() * sizeof(uint64_t));
+    memcpy(h + offs[w][2], gp.lfsr.data(), gp.lfsr.size() * sizeof(uint32_t));
+    if (!gp.apply.empty())
+      memcpy(h + offs[w][3], gp.apply.data(), gp.apply.size() * sizeof(uint32_t));
+    if (hipMemcpyAsync(groups[w].arena, h, upload_len[w], hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return RS_EDEVICE;
+    hipGraphExec_t exec;
+    rc = graph_for(op, w, launch[op][w], &exec);
+    if (rc != RS_OK) return rc;
+    if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
+  }
+  if (hipEventRecord(staging_free, st) != hipSuccess) return RS_EDEVICE;
+  staging_pending = true;
+  return RS_OK;
+}
+
+namespace rsp {
+namespace {
+
+// ------------------------------------------------------------- tuning --
+
+std::string cache_key(const std::string &arch, int op, int wide, int bucket) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "\"arch\": \"%s\", \"op\": %d, \"wide\": %d, \"bucket\": %d",
+           arch.c_str(), op, wide, bucket);
+  return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, rs_poly_launch_t *out) {
+  FILE *f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    if (!strstr(line, key.c_str())) continue;
+    rs_poly_launch_t c;
+    const char *p = strstr(line, "\"bytes_per_lane\":");
+    if (!p || sscanf(p, "\"bytes_per_lane\": %d, \"threads\": %d, \"tile_bytes\": %d, "
+                        "\"wgs_per_cu\": %d", &c.bytes_per_lane, &c.threads, &c.tile_bytes,
+                     &c.wgs_per_cu) != 4)
+      continue;
+    *out = c;
+    found = true;  // the last matching line wins
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_store(const char *path, const std::string &key, const rs_poly_launch_t &c,
+                 double ms) {
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f,
+          "{%s, \"bytes_per_lane\": %d, \"threads\": %d, \"tile_bytes\": %d, "
+          "\"wgs_per_cu\": %d, \"ms\": %.4f}\n",
+          key.c_str(), c.bytes_per_lane, c.threads, c.tile_bytes, c.wgs_per_cu, ms);
+  fclose(f);
+}
+
+}  // namespace
+}  // namespace rsp
+
+extern "C" {
+
+int rs_poly_batch_create(rs_poly_batch_t **out) {
+  if (!out) return RS_ENULL;
+  *out = nullptr;
+  rs_poly_batch_t *b = new (std::nothrow) rs_poly_batch_t;
+  if (!b) return RS_ENOMEM;
+  for (int op = 0; op < kOps; ++op)
+    for (int w = 0; w < kWidths; ++w) b->launch[op][w] = default_launch(op, w);
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipGetDeviceProperties(&prop, b->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->staging_free, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return RS_EDEVICE;
+  }
+  b->num_cu = prop.multiProcessorCount;
+  b->arch = prop.gcnArchName;
+  const size_t colon = b->arch.find(':');
+  if (colon != std::string::npos) b->arch.resize(colon);
+  *out = b;
+  return RS_OK;
+}
+
+void rs_poly_batch_free(rs_poly_batch_t *b) { delete b; }
+
+int rs_poly_batch_encode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, int count,
+                         void *stream) {
+  if (!b) return RS_ENULL;
+  std::lock_guard<std::mutex> lock(b->mu);
+  return b->run(RS_POLY_OP_ENCODE, stripes, count, stream);
+}
+
+int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, int count,
+                         void *stream) {
+  if (!b) return RS_ENULL;
+  std::lock_guard<std::mutex> lock(b->mu);
+  return b->run(RS_POLY_OP_DECODE, stripes, count, stream);
+}
+
+int rs_poly_batch_get_launch(const rs_poly_batch_t *b, int op, int wide, rs_poly_launch_t *cfg) {
+  if (!b || !cfg) return RS_ENULL;
+  if (op < 0 || op >= kOps || wide < 0 || wide >= kWidths) return RS_EINVAL;
+  *cfg = b->launch[op][wide];
+  return RS_OK;
+}
+
+int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide, const rs_poly_launch_t *cfg) {
+  if (!b || !cfg) return RS_ENULL;
+  if (op < 0 || op >= kOps || wide < 0 || wide >= kWidths) return RS_EINVAL;
+  if (!valid_launch(op, wide, *cfg)) return RS_EINVAL;
+  std::lock_guard<std::mutex> lock(b->mu);
+  b->launch[op][wide] = *cfg;
+  return RS_OK;
+}
+
+int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, int count,
+                 void *stream, rs_poly_launch_t *best) {
+  if (!b) return RS_ENULL;
+  if (op != RS_POLY_OP_ENCODE && op != RS_POLY_OP_DECODE) return RS_EINVAL;
+  if (count < 0) return RS_EINVAL;
+  if (count > 0 && !stripes) return RS_ENULL;
+  std::lock_guard<std::mutex> lock(b->mu);
+
+  // Split the stripes by state width; tune each width on its own stripes.
+  std::vector<rs_poly_stripe_t> sub[kWidths];
+  double bytes[kWidths] = {0, 0};
+  for (int i = 0; i < count; ++i) {
+    if (!stripes[i].code) return RS_ENULL;
+    const int w = stripes[i].code->code.state_bytes() == 8;
+    sub[w].push_back(stripes[i]);
+    bytes[w] += (double)stripes[i].code->code.k() * stripes[i].block_bytes;
+  }
+  const char *cache = getenv("RS_POLY_TUNE_CACHE");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RS_EDEVICE;
+  int status = RS_OK;
+  for (int w = 0; w < kWidths && status == RS_OK; ++w) {
+    if (sub[w].empty()) continue;
+    const double mean = bytes[w] / sub[w].size() /
+                        std::max(1, sub[w][0].code->code.k());
+    const int bucket = mean >= 1 ? (int)std::floor(std::log2(mean)) : 0;
+    const std::string key = cache_key(b->arch, op, w, bucket);
+    rs_poly_launch_t cached;
+    if (cache && cache_lookup(cache, key, &cached) && valid_launch(op, w, cached)) {
+      b->launch[op][w] = cached;
+      continue;
+    }
+    rs_poly_launch_t winner = b->launch[op][w];
+    double winner_ms = 1e30;
+    const int bpls[] = {4, 8, 16};
+    const int threads[] = {256, 512, 1024};
+    const int tiles[] = {16 << 10, 64 << 10, 256 << 10};
+    for (int bpl : bpls)
+      for (int th : threads)
+        for (int tile : tiles)
+          for (int wgs = 1; wgs <= 2; ++wgs) {
+            const rs_poly_launch_t c{bpl, th, tile, wgs};
+            if (!valid_launch(op, w, c)) continue;
+            b->launch[op][w] = c;
+            // one warm-up (also captures the graph), then 3 timed runs
+            double ms = 0;
+            for (int rep = 0; rep < 4 && status == RS_OK; ++rep) {
+              if (rep == 1) (void)hipEventRecord(e0, st);
+              status = b->run(op, sub[w].data(), (int)sub[w].size(), stream);
+            }
+            if (status != RS_OK) break;
+            (void)hipEventRecord(e1, st);
+            float f = 0;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess) {
+              status = RS_EDEVICE;
+              break;
+            }
+            ms = f / 3.0;
+            if (ms < winner_ms) {
+              winner_ms = ms;
+              winner = c;
+            }
+          }
+    b->launch[op][w] = winner;
+    if (cache && status == RS_OK) cache_store(cache, key, winner, winner_ms);
+  }
+  // Keep only what later calls use; the winners' graphs are captured again.
+  if (status == RS_OK && hipStreamSynchronize(st) == hipSuccess) b->drop_graphs();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == RS_OK && best) {
+    const int w = bytes[1] > bytes[0] ? 1 : 0;
+    *best = b->launch[op][w];
+  }
+  return status;
+}
+
+}  // extern "C"

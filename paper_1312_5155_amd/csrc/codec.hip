@@ -34,10 +34,15 @@
 //
 // LDS tables.  Each table is a GF(2)-linear map of one byte, expanded by
 // every workgroup from 8 basis values passed in the kernel arguments.  Entry
-// e of every table sits at byte e*256 (plus a per-table offset and a
-// per-lane replica), so v_perm_b32(state, lane_offset) yields the address
-// directly; replicas spread the 16 lanes of a quarter-wave over distinct
-// banks.
+// e of every table sits at byte e*256 (plus a per-table offset, an
+// immediate of the LDS read, and a per-lane replica), so one v_perm_b32 of
+// (state, lane offset) yields the address; replicas spread the lanes of a
+// wave over banks.  64 KiB per workgroup, two workgroups per CU.
+//
+// Memory-level parallelism.  The kernels stream every byte once; throughput
+// is set by the bytes in flight per CU.  Each lane walks its column chunks
+// as a software pipeline that keeps the loads of the next M blocks in
+// flight while the current M are absorbed.
 #include <hip/hip_runtime.h>
 
 #include "rs_internal.h"
@@ -96,64 +101,94 @@ __device__ __forceinline__ void st4(uint8_t *lds, uint32_t off, uint32_t a, uint
   *reinterpret_cast<uint4 *>(lds + off) = make_uint4(a, b, c, d);
 }
 
-// Expands the LFSR tables: 4 rotated copies of T', each 16 (M=4, 4-byte
-// values) or 8 (M=8, 8-byte values) replicas wide, 64 bytes per copy per row.
-template <int M>
+// LDS row layout.  Row e (256 bytes at e*256) holds entry e of every table.
+// Encode: 4 rotated copies of T', each kLfsrReps replicas wide.  Decode: the
+// same 4 copies at half the replication in bytes 0..127, and the apply
+// tables U'_b (one per remainder byte) in bytes 128..255.
+template <int M, int MODE>
+struct Layout {
+  static constexpr uint32_t kEntry = M == 4 ? 4 : 8;              // bytes per value
+  static constexpr uint32_t kLfsrReps = (MODE == kEncode ? 256 : 128) / (4 * kEntry);
+  static constexpr uint32_t kCopyBytes = kLfsrReps * kEntry;      // one rotated copy
+  static constexpr uint32_t kApplyReps = 128 / (M * kEntry);      // decode only
+  static constexpr uint32_t kTableBytes = kApplyReps * kEntry;    // one apply table
+  static constexpr uint32_t kApplyBase = 128;
+};
+
+// Expands the LFSR tables: copy v (0..3) of entry f is rotl(T'[f], 8(v+1)).
+template <int M, int MODE>
 __device__ void build_lfsr_tables(uint8_t *lds, const uint32_t *basis) {
+  using L = Layout<M, MODE>;
   for (uint32_t idx = threadIdx.x; idx < 1024; idx += blockDim.x) {
     const uint32_t f = idx >> 2, v = idx & 3;
-    const uint32_t base = f * kRowBytes + v * 64;
+    const uint32_t base = f * kRowBytes + v * L::kCopyBytes;
+    uint32_t lo, hi;
     if constexpr (M == 4) {
-      const uint32_t x = rotl32(lin32(f, basis), 8 * (v + 1));
-#pragma unroll
-      for (int r = 0; r < 4; ++r) st4(lds, base + 16 * r, x, x, x, x);
+      lo = hi = rotl32(lin32(f, basis), 8 * (v + 1));
     } else {
       const uint64_t x = rotl64(lin64(f, basis), 8 * (v + 1));
-      const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) st4(lds, base + 16 * r, lo, hi, lo, hi);
+      lo = (uint32_t)x;
+      hi = (uint32_t)(x >> 32);
     }
+#pragma unroll
+    for (uint32_t r = 0; r < L::kCopyBytes / 16; ++r)
+      st4(lds, base + 16 * r, lo, hi, lo, hi);
   }
 }
 
-// Expands the decode apply tables U'_b (one per remainder byte b < m): for
-// M=4, 4 tables x 16 replicas; for M=8, 8 tables x 4 replicas.
+// Expands the decode apply tables U'_b, b < m (unused tables are zero).
 template <int M>
-__device__ void build_apply_tables(uint8_t *lds, const CodecParams &p) {
-  constexpr uint32_t kTables = M;
-  for (uint32_t idx = threadIdx.x; idx < 256 * kTables; idx += blockDim.x) {
-    const uint32_t f = idx / kTables, b = idx % kTables;
-    const bool used = (int)b < p.m;
+__device__ void build_apply_tables(uint8_t *lds, const uint32_t *basis /* [kMaxM][16] */,
+                                   int m) {
+  using L = Layout<M, kDecode>;
+  for (uint32_t idx = threadIdx.x; idx < 256 * M; idx += blockDim.x) {
+    const uint32_t f = idx / M, b = idx % M;
+    const bool used = (int)b < m;
+    const uint32_t base = f * kRowBytes + L::kApplyBase + b * L::kTableBytes;
+    uint32_t lo, hi;
     if constexpr (M == 4) {
-      const uint32_t base = kApplyRegion + f * kRowBytes + b * 64;
-      const uint32_t x = used ? lin32(f, p.apply_basis[b]) : 0u;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) st4(lds, base + 16 * r, x, x, x, x);
+      lo = hi = used ? lin32(f, basis + 16 * b) : 0u;
     } else {
-      const uint32_t base = kApplyRegion + f * kRowBytes + b * 32;
-      const uint64_t x = used ? lin64(f, p.apply_basis[b]) : 0ull;
-      const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-      st4(lds, base, lo, hi, lo, hi);
-      st4(lds, base + 16, lo, hi, lo, hi);
+      const uint64_t x = used ? lin64(f, basis + 16 * b) : 0ull;
+      lo = (uint32_t)x;
+      hi = (uint32_t)(x >> 32);
     }
+#pragma unroll
+    for (uint32_t r = 0; r < L::kTableBytes / 16; ++r) st4(lds, base + 16 * r, lo, hi, lo, hi);
   }
 }
 
-// Loads W dwords (4*W byte columns starting at col) of one block; columns
-// past the end of the block read as zero.
+// Block pointers always address global memory; saying so keeps the
+// compiler on global (not flat) loads and stores, which leave the LDS
+// wait counter alone.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ global_ptr<T> as_global(T *p) {
+  return (global_ptr<T>)(uintptr_t)p;
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Loads W dwords (4*W byte columns starting at col) of one block.  The
+// vector form needs the whole chunk inside the block; the byte form reads
+// columns past the end of the block as zero.
 template <int W, bool BYTEWISE>
-__device__ __forceinline__ void load_cols(const uint8_t *ptr, uint64_t col, uint64_t B,
+__device__ __forceinline__ void load_cols(const uint8_t *ptr, uint32_t col, uint32_t B,
                                           uint32_t (&a)[W]) {
-  if (!BYTEWISE && col + 4 * W <= B) {
-    const uint8_t *q = ptr + col;
+  const global_ptr<const uint8_t> g = as_global(ptr);
+  if (!BYTEWISE) {
+    const global_ptr<const uint8_t> q = g + col;
     if constexpr (W == 4) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(q);
+      const u32x4 v = *(const global_ptr<const u32x4>)q;
       a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
     } else if constexpr (W == 2) {
-      const uint2 v = *reinterpret_cast<const uint2 *>(q);
+      const u32x2 v = *(const global_ptr<const u32x2>)q;
       a[0] = v.x; a[1] = v.y;
     } else {
-      a[0] = *reinterpret_cast<const uint32_t *>(q);
+      a[0] = *(const global_ptr<const uint32_t>)q;
     }
   } else {
 #pragma unroll
@@ -161,8 +196,8 @@ __device__ __forceinline__ void load_cols(const uint8_t *ptr, uint64_t col, uint
       uint32_t v = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint64_t c = col + 4 * d + i;
-        if (c < B) v |= (uint32_t)ptr[c] << (8 * i);
+        const uint32_t c = col + 4 * d + i;
+        if (c < B) v |= (uint32_t)g[c] << (8 * i);
       }
       a[d] = v;
     }
@@ -170,41 +205,44 @@ __device__ __forceinline__ void load_cols(const uint8_t *ptr, uint64_t col, uint
 }
 
 template <int W, bool BYTEWISE>
-__device__ __forceinline__ void store_cols(uint8_t *ptr, uint64_t col, uint64_t B,
+__device__ __forceinline__ void store_cols(uint8_t *ptr, uint32_t col, uint32_t B,
                                            const uint32_t (&a)[W]) {
-  if (!BYTEWISE && col + 4 * W <= B) {
-    uint8_t *q = ptr + col;
+  const global_ptr<uint8_t> g = as_global(ptr);
+  if (!BYTEWISE) {
+    const global_ptr<uint8_t> q = g + col;
     if constexpr (W == 4) {
-      *reinterpret_cast<uint4 *>(q) = make_uint4(a[0], a[1], a[2], a[3]);
+      *(global_ptr<u32x4>)q = u32x4{a[0], a[1], a[2], a[3]};
     } else if constexpr (W == 2) {
-      *reinterpret_cast<uint2 *>(q) = make_uint2(a[0], a[1]);
+      *(global_ptr<u32x2>)q = u32x2{a[0], a[1]};
     } else {
-      *reinterpret_cast<uint32_t *>(q) = a[0];
+      *(global_ptr<uint32_t>)q = a[0];
     }
   } else {
 #pragma unroll
     for (int d = 0; d < W; ++d) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint64_t c = col + 4 * d + i;
-        if (c < B) ptr[c] = (uint8_t)(a[d] >> (8 * i));
+        const uint32_t c = col + 4 * d + i;
+        if (c < B) g[c] = (uint8_t)(a[d] >> (8 * i));
       }
     }
   }
 }
 
 // One LFSR step at window position q (compile time) for one column.
-template <int M>
+template <int M, int MODE>
 __device__ __forceinline__ void lfsr_step(uint32_t (&s)[M / 4], const uint8_t *lds,
                                           uint32_t loff, int q) {
+  using L = Layout<M, MODE>;
   const int bp = q & 3;
+  const uint32_t sel = 0x0C0C0400u | ((uint32_t)bp << 8);
   if constexpr (M == 4) {
-    const uint32_t addr = perm(s[0], loff, 0x0C0C0400u | ((uint32_t)bp << 8));
-    s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr + bp * 64);
+    const uint32_t addr = perm(s[0], loff, sel);
+    s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr + bp * L::kCopyBytes);
   } else {
     const int half = q >> 2;
-    const uint32_t addr = perm(s[half], loff, 0x0C0C0400u | ((uint32_t)bp << 8));
-    const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr + bp * 64);
+    const uint32_t addr = perm(s[half], loff, sel);
+    const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr + bp * L::kCopyBytes);
     if (half == 0) {
       s[0] ^= v.x;
       s[1] ^= v.y;
@@ -215,144 +253,383 @@ __device__ __forceinline__ void lfsr_step(uint32_t (&s)[M / 4], const uint8_t *l
   }
 }
 
-template <int M, int W, int MODE, bool BYTEWISE>
-__global__ void __launch_bounds__(1024) codec_kernel(CodecParams p) {
-  constexpr int NQ = M / 4;   // dwords of state per column
-  constexpr int NC = 4 * W;   // columns per lane
-  __shared__ __attribute__((aligned(16))) uint8_t lds[MODE == kDecode ? 131072 : 65536];
+// Where one stripe's blocks are: kernel arguments (plain launch) or a
+// pointer table in device memory (batched launch).
+struct PlainSrc {
+  const CodecParams &p;
+  __device__ const uint8_t *data(int j) const { return p.data[j]; }
+  __device__ const uint8_t *par_in(int i) const { return p.par_in[i]; }
+  __device__ uint8_t *out(int o) const { return p.out[o]; }
+  __device__ uint32_t B() const { return p.block_bytes; }
+  __device__ int k() const { return p.k; }
+  __device__ int m() const { return p.m; }
+  __device__ int k_pad() const { return p.k_pad; }
+  __device__ int n_out() const { return p.n_out; }
+  __device__ const uint8_t *zero() const { return p.zero_page; }
+};
 
-  build_lfsr_tables<M>(lds, p.lfsr_basis);
-  if constexpr (MODE == kDecode) build_apply_tables<M>(lds, p);
-  __syncthreads();
+// Batch tables (pointers, descriptors, bases, tile map) never change while
+// a batch kernel runs: reading them through the constant address space lets
+// the compiler use scalar loads for uniform indices.
+template <class T>
+using const_as = const __attribute__((address_space(4))) T *;
 
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t loff = M == 4 ? (lane & 15) * 4 : (lane & 7) * 8;
-  const uint64_t B = p.block_bytes;
-  const uint64_t nchunks = (B + NC - 1) / NC;
-  const int groups = p.k_pad / M;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+template <class T>
+__device__ __forceinline__ const_as<T> as_const(const T *p) {
+  return (const_as<T>)(uintptr_t)p;
+}
 
-  for (uint64_t ch = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < nchunks;
-       ch += stride) {
-    const uint64_t col = ch * NC;
-    uint32_t s[NC][NQ];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int h = 0; h < NQ; ++h) s[c][h] = 0;
+__device__ __forceinline__ StripeDesc load_desc(const_as<StripeDesc> p) {
+  StripeDesc d;
+  d.block_bytes = p->block_bytes;
+  d.tile_begin = p->tile_begin;
+  d.ptr_off = p->ptr_off;
+  d.lfsr_set = p->lfsr_set;
+  d.apply_set = p->apply_set;
+  d.k = p->k;
+  d.m = p->m;
+  d.k_pad = p->k_pad;
+  d.n_out = p->n_out;
+  return d;
+}
 
-    for (int g = 0; g < groups; ++g) {
-      // M symbols per column: window position q takes block k_pad-1-(g*M+q).
-      uint32_t a[M][W];
+struct TableSrc {
+  const_as<uint64_t> ptrs;   // k data, then m parity inputs, then n_out outputs
+  uint32_t bytes;
+  int kk, mm, kp, no;
+  const uint8_t *zp;
+  __device__ const uint8_t *data(int j) const {
+    return reinterpret_cast<const uint8_t *>(ptrs[j]);
+  }
+  __device__ const uint8_t *par_in(int i) const {
+    return reinterpret_cast<const uint8_t *>(ptrs[kk + i]);
+  }
+  __device__ uint8_t *out(int o) const { return reinterpret_cast<uint8_t *>(ptrs[kk + mm + o]); }
+  __device__ uint32_t B() const { return bytes; }
+  __device__ int k() const { return kk; }
+  __device__ int m() const { return mm; }
+  __device__ int k_pad() const { return kp; }
+  __device__ int n_out() const { return no; }
+  __device__ const uint8_t *zero() const { return zp; }
+};
+
+// Loads item g of a column chunk: for g < k_pad/M the M data blocks of LFSR
+// group g (window position q holds block k_pad-1-(g*M+q)); for decode, item
+// k_pad/M holds the parity read, position b holding p_(m-1-b).  Blocks not
+// read (erased, unread, padding) give zeros.  In the vector form every slot
+// issues its load -- an absent block reads the zero page at an offset kept
+// inside it -- so the number of loads in flight never depends on the path
+// and the compiler can wait for exactly the item it is about to use.
+template <int M, int W, int MODE, bool BYTEWISE, class Src>
+__device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, int groups,
+                                          uint32_t (&a)[M][W]) {
+  const uint32_t B = src.B();
 #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const int j = p.k_pad - 1 - (g * M + q);
-        const uint8_t *ptr = j < p.k ? p.data[j] : nullptr;
-        if (ptr) {
-          load_cols<W, BYTEWISE>(ptr, col, B, a[q]);
-        } else {
-#pragma unroll
-          for (int w = 0; w < W; ++w) a[q][w] = 0;
-        }
-      }
-      // Transpose so that each column's M symbols fill its state window.
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-#pragma unroll
-        for (int h = 0; h < NQ; ++h) {
-          uint32_t d0, d1, d2, d3;
-          transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d0, d1,
-                     d2, d3);
-          s[4 * w + 0][h] ^= d0;
-          s[4 * w + 1][h] ^= d1;
-          s[4 * w + 2][h] ^= d2;
-          s[4 * w + 3][h] ^= d3;
-        }
-#pragma unroll
-      for (int q = 0; q < M; ++q)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) lfsr_step<M>(s[c], lds, loff, q);
+  for (int q = 0; q < M; ++q) {
+    const uint8_t *ptr;
+    if (MODE == kDecode && g == groups) {
+      const int i = src.m() - 1 - q;
+      ptr = i >= 0 ? src.par_in(i) : nullptr;
+    } else {
+      const int j = src.k_pad() - 1 - (g * M + q);
+      ptr = j < src.k() ? src.data(j) : nullptr;
     }
-    // k_pad is a multiple of M: the rotation is back at 0 and byte b of the
-    // state is remainder coefficient r_(m-1-b).
-
-    if constexpr (MODE == kDecode) {
-      // Add the parity symbols read: p_i is coefficient i of the received
-      // word, i.e. byte m-1-i of the state.
+    if constexpr (BYTEWISE) {
+      if (ptr) {
+        load_cols<W, true>(ptr, col, B, a[q]);
+      } else {
 #pragma unroll
-      for (int h = 0; h < NQ; ++h) {
-        uint32_t a[4][W];
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-          const int i = p.m - 1 - (4 * h + bb);
-          const uint8_t *ptr = i >= 0 ? p.par_in[i] : nullptr;
-          if (ptr) {
-            load_cols<W, BYTEWISE>(ptr, col, B, a[bb]);
-          } else {
-#pragma unroll
-            for (int w = 0; w < W; ++w) a[bb][w] = 0;
-          }
-        }
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          uint32_t d0, d1, d2, d3;
-          transpose4(a[0][w], a[1][w], a[2][w], a[3][w], d0, d1, d2, d3);
-          s[4 * w + 0][h] ^= d0;
-          s[4 * w + 1][h] ^= d1;
-          s[4 * w + 2][h] ^= d2;
-          s[4 * w + 3][h] ^= d3;
-        }
+        for (int w = 0; w < W; ++w) a[q][w] = 0;
       }
-      // Rebuilt symbol e = byte e of sum_b U'_b[byte b of the remainder].
-      const uint32_t aoff = (M == 4 ? (lane & 15) * 4 : (lane & 3) * 8) | kApplyRegion;
-      uint32_t L[NC][NQ];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int h = 0; h < NQ; ++h) L[c][h] = 0;
-#pragma unroll
-      for (int b = 0; b < M; ++b) {
-        if (b < p.m) {
-          const uint32_t sel = 0x0C020400u | ((uint32_t)(b & 3) << 8);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            const uint32_t addr = perm(s[c][b >> 2], aoff, sel);
-            if constexpr (M == 4) {
-              L[c][0] ^= *reinterpret_cast<const uint32_t *>(lds + addr + b * 64);
-            } else {
-              const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr + b * 32);
-              L[c][0] ^= v.x;
-              L[c][1] ^= v.y;
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int h = 0; h < NQ; ++h) s[c][h] = L[c][h];
-    }
-
-    // Byte b of s[c] goes to column c of output o, where o = m-1-b for
-    // encode (parity p_o) and o = b for decode (erased block o).
-#pragma unroll
-    for (int h = 0; h < NQ; ++h) {
-      uint32_t o[4][W];
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-        transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
-                   o[1][w], o[2][w], o[3][w]);
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const int b = 4 * h + bb;
-        const int oi = MODE == kEncode ? p.m - 1 - b : b;
-        if (oi >= 0 && oi < p.n_out) store_cols<W, BYTEWISE>(p.out[oi], col, B, o[bb]);
-      }
+    } else {
+      const bool absent = ptr == nullptr;
+      load_cols<W, false>(absent ? src.zero() : ptr, absent ? col & (kZeroPageBytes - 16) : col,
+                          B, a[q]);
     }
   }
 }
 
+// XORs an item into the column states (transposed so that each column's M
+// symbols fill its state window), then, for an LFSR group, runs its M steps.
+template <int M, int W, int MODE>
+__device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
+                                            bool lfsr, const uint8_t *lds, uint32_t loff) {
+  constexpr int NQ = M / 4;
+  constexpr int NC = 4 * W;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int h = 0; h < NQ; ++h) {
+      uint32_t d0, d1, d2, d3;
+      transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d0, d1, d2, d3);
+      s[4 * w + 0][h] ^= d0;
+      s[4 * w + 1][h] ^= d1;
+      s[4 * w + 2][h] ^= d2;
+      s[4 * w + 3][h] ^= d3;
+    }
+  if (lfsr) {
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) lfsr_step<M, MODE>(s[c], lds, loff, q);
+  }
+}
+
+// After the last item of a chunk: byte b of the state is remainder
+// coefficient r_(m-1-b) (plus the parity read, for decode).  Decode maps it
+// through the apply tables; the result is transposed back to blocks and
+// stored: encode writes parity p_(m-1-b) from byte b, decode writes erased
+// block e from byte e.
+template <int M, int W, int MODE, bool BYTEWISE, class Src>
+__device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool active,
+                                             uint32_t (&s)[4 * W][M / 4], const uint8_t *lds,
+                                             uint32_t aoff) {
+  constexpr int NQ = M / 4;
+  constexpr int NC = 4 * W;
+  const int m = src.m(), n_out = src.n_out();
+  if constexpr (MODE == kDecode) {
+    uint32_t L[NC][NQ];   // packed rebuilt symbols
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int h = 0; h < NQ; ++h) L[c][h] = 0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      if (b < m) {
+        constexpr uint32_t base = Layout<M, kDecode>::kApplyBase;
+        const uint32_t tab = base + b * Layout<M, kDecode>::kTableBytes;
+        const uint32_t sel = 0x0C0C0400u | ((uint32_t)(b & 3) << 8);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const uint32_t addr = perm(s[c][b >> 2], aoff, sel);
+          if constexpr (M == 4) {
+            L[c][0] ^= *reinterpret_cast<const uint32_t *>(lds + addr + tab);
+          } else {
+            const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr + tab);
+            L[c][0] ^= v.x;
+            L[c][1] ^= v.y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int h = 0; h < NQ; ++h) s[c][h] = L[c][h];
+  }
+#pragma unroll
+  for (int h = 0; h < NQ; ++h) {
+    uint32_t o[4][W];
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
+                 o[1][w], o[2][w], o[3][w]);
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const int b = 4 * h + bb;
+      const int oi = MODE == kEncode ? m - 1 - b : b;
+      if (oi >= 0 && oi < n_out && active)
+        store_cols<W, BYTEWISE>(src.out(oi), col, src.B(), o[bb]);
+    }
+  }
+}
+
+// Encodes or decodes chunks c0 + (r*lanes + lane)*NC, r = 0, 1, ..., of one
+// stripe, for the n chunks starting at c0.  Control flow is uniform: every
+// lane runs the same rounds, and a lane whose chunk index is past n works on
+// chunk c0 again and stores nothing, so block pointers stay in SGPRs and
+// the loads need no branches.  The walk is a software pipeline over items
+// (LFSR groups, then for decode the parity item): the loads of the next
+// item, also across chunks, are issued before the current item goes through
+// the LFSR, so each lane keeps up to 2*M block loads in flight.
+template <int M, int W, int MODE, bool BYTEWISE, class Src>
+__device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uint32_t n,
+                                                uint32_t lane, uint32_t lanes,
+                                                const uint8_t *lds, uint32_t loff,
+                                                uint32_t aoff) {
+  constexpr uint32_t NC = 4 * W;
+  if (n == 0) return;
+  const int groups = src.k_pad() / M;
+  const int items = groups + (MODE == kDecode ? 1 : 0);
+  const uint32_t rounds = (n + lanes - 1) / lanes;
+  auto col_of = [&](uint32_t r) {
+    const uint32_t idx = r * lanes + lane;
+    return idx < n ? c0 + idx * NC : c0;
+  };
+
+  uint32_t s[4 * W][M / 4];
+  uint32_t a[M][W], b[M][W];
+#pragma unroll
+  for (int c = 0; c < 4 * W; ++c)
+#pragma unroll
+    for (int h = 0; h < M / 4; ++h) s[c][h] = 0;
+
+  uint32_t r = 0;   // round of the current item (uniform)
+  int g = 0;        // item within the chunk (uniform)
+  load_item<M, W, MODE, BYTEWISE>(src, col_of(0), 0, groups, a);
+
+  // One pipeline stage: prefetch the item after (r, g) into nxt, consume cur.
+  auto stage = [&](uint32_t (&cur)[M][W], uint32_t (&nxt)[M][W]) -> bool {
+    uint32_t nr = r;
+    int ng = g + 1;
+    if (ng == items) {
+      ng = 0;
+      ++nr;
+    }
+    const bool more = nr < rounds;
+    // past the last item the prefetch repeats the current one (and is unused)
+    load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, nxt);
+    absorb_item<M, W, MODE>(s, cur, g < groups, lds, loff);
+    if (g == items - 1) {
+      finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, aoff);
+#pragma unroll
+      for (int c = 0; c < 4 * W; ++c)
+#pragma unroll
+        for (int h = 0; h < M / 4; ++h) s[c][h] = 0;
+    }
+    r = nr;
+    g = ng;
+    return more;
+  };
+  for (;;) {
+    if (!stage(a, b)) break;
+    if (!stage(b, a)) break;
+  }
+}
+
+// Columns [c0, c1) of one stripe: full chunks by all lanes, then the last
+// partial chunk (fewer than 4*W columns, only at the end of a block) by one
+// thread with byte loads and stores.
+template <int M, int W, int MODE, class Src>
+__device__ __forceinline__ void process_range(const Src &src, uint32_t c0, uint32_t c1,
+                                              uint32_t lane, uint32_t lanes, const uint8_t *lds,
+                                              uint32_t loff, uint32_t aoff) {
+  constexpr uint32_t NC = 4 * W;
+  const uint32_t n_full = (c1 - c0) / NC;
+  process_columns<M, W, MODE, false>(src, c0, n_full, lane, lanes, lds, loff, aoff);
+  const uint32_t tail = c0 + n_full * NC;
+  if (tail < c1 && lane == 0)
+    process_columns<M, 1, MODE, true>(src, tail, (c1 - tail + 3) / 4, 0, 1, lds, loff, aoff);
+}
+
+template <int M, int MODE>
+__device__ __forceinline__ uint32_t lfsr_lane_offset() {
+  using L = Layout<M, MODE>;
+  return (threadIdx.x & (L::kLfsrReps - 1)) * L::kEntry;
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t apply_lane_offset() {
+  using L = Layout<M, kDecode>;
+  return (threadIdx.x & (L::kApplyReps - 1)) * L::kEntry;
+}
+
+constexpr uint32_t kLdsBytes = 256 * kRowBytes;
+
+// Workgroup size bound per variant: the 16-byte-per-lane variants hold two
+// items of loads in flight and need more than 128 VGPRs.
+template <int M, int W>
+constexpr int max_threads() {
+  return W == 4 ? (M == 8 ? 256 : 512) : 1024;
+}
+
+// One stripe per launch: grid-stride loop over its column chunks.
+template <int M, int W, int MODE, bool BYTEWISE>
+__global__ void __launch_bounds__((max_threads<M, W>()))
+__attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) codec_kernel(CodecParams p) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+  build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
+  if constexpr (MODE == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
+  __syncthreads();
+
+  constexpr uint32_t NC = 4 * W;
+  const PlainSrc src{p};
+  const uint32_t loff = lfsr_lane_offset<M, MODE>(), aoff = apply_lane_offset<M>();
+  const uint32_t lane = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lanes = gridDim.x * blockDim.x;
+  const uint32_t B = (uint32_t)p.block_bytes;
+  if constexpr (BYTEWISE)
+    process_columns<M, W, MODE, true>(src, 0, (B + NC - 1) / NC, lane, lanes, lds, loff, aoff);
+  else
+    process_range<M, W, MODE>(src, 0, B, lane, lanes, lds, loff, aoff);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+// Fills the tile -> stripe map of a batch group and clears its tile
+// counter; runs before the persistent kernel in the same graph.
+__global__ void batch_prepare_kernel(BatchGroup g) {
+  BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
+  const StripeDesc *descs = reinterpret_cast<const StripeDesc *>(g.arena + hdr->off_descs);
+  const uint32_t n = hdr->n_stripes;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) hdr->counter = 0;
+  if (s >= n) return;
+  const uint64_t t0 = descs[s].tile_begin;
+  const uint64_t t1 = s + 1 < n ? descs[s + 1].tile_begin : hdr->total_tiles;
+  for (uint64_t t = t0; t < t1; ++t) g.tile_stripe[t] = s;
+}
+
+// Persistent kernel over every tile of a batch group.  Each workgroup takes
+// the next tile from an atomic counter (prefetched one tile ahead), finds its
+// stripe through the tile map, re-expands the LDS tables only when the
+// stripe's code or erasure pattern differs from the one staged, and encodes
+// or decodes the tile's columns.  Every wave leaves the loop once the counter
+// passes the last tile.
+template <int M, int W, int MODE>
+__global__ void __launch_bounds__((max_threads<M, W>()))
+__attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+  __shared__ uint64_t next_tile;
+  BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
+  const_as<BatchHeader> chdr = as_const(hdr);
+  const uint64_t total = chdr->total_tiles;
+  const_as<StripeDesc> descs = as_const(reinterpret_cast<const StripeDesc *>(g.arena + chdr->off_descs));
+  const_as<uint64_t> ptr_table = as_const(reinterpret_cast<const uint64_t *>(g.arena + chdr->off_ptrs));
+  const uint32_t *lfsr_sets = reinterpret_cast<const uint32_t *>(g.arena + chdr->off_lfsr);
+  const uint32_t *apply_sets = reinterpret_cast<const uint32_t *>(g.arena + chdr->off_apply);
+  const_as<uint32_t> tile_stripe = as_const(g.tile_stripe);
+  unsigned long long *counter = reinterpret_cast<unsigned long long *>(&hdr->counter);
+  const uint32_t tile_cols = g.tile_cols;
+  const uint32_t loff = lfsr_lane_offset<M, MODE>(), aoff = apply_lane_offset<M>();
+  uint32_t staged_lfsr = ~0u, staged_apply = ~0u;
+
+  if (threadIdx.x == 0) next_tile = atomicAdd(counter, 1ull);
+  __syncthreads();
+  for (;;) {
+    const uint64_t tile =
+        (uint64_t)uniform((uint32_t)(next_tile >> 32)) << 32 | uniform((uint32_t)next_tile);
+    __syncthreads();   // every thread has read next_tile
+    if (tile >= total) break;
+    if (threadIdx.x == 0) next_tile = atomicAdd(counter, 1ull);
+
+    const uint32_t s = tile_stripe[tile];
+    const StripeDesc d = load_desc(descs + s);
+    const bool new_lfsr = d.lfsr_set != staged_lfsr;
+    const bool new_apply = MODE == kDecode && d.apply_set != staged_apply;
+    if (new_lfsr || new_apply) {
+      // The barrier at the end of the previous tile guarantees no wave still
+      // reads the old tables.
+      if (new_lfsr) build_lfsr_tables<M, MODE>(lds, lfsr_sets + 16 * d.lfsr_set);
+      if (new_apply) build_apply_tables<M>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.m);
+      staged_lfsr = d.lfsr_set;
+      staged_apply = d.apply_set;
+      __syncthreads();
+    }
+
+    const uint32_t bytes = (uint32_t)d.block_bytes;
+    const TableSrc src{ptr_table + d.ptr_off, bytes, d.k, d.m, d.k_pad, d.n_out, g.zero_page};
+    const uint32_t c0 = (uint32_t)(tile - d.tile_begin) * tile_cols;
+    const uint32_t c1 = bytes - c0 > tile_cols ? c0 + tile_cols : bytes;
+    process_range<M, W, MODE>(src, c0, c1, threadIdx.x, blockDim.x, lds, loff, aoff);
+    __syncthreads();   // tables and next_tile are about to change
+  }
+}
+
 using KernelFn = void (*)(CodecParams);
+using BatchFn = void (*)(BatchGroup);
 
 template <int MODE>
 KernelFn pick(int sb, int w, bool bytewise) {
@@ -362,20 +639,55 @@ KernelFn pick(int sb, int w, bool bytewise) {
     if (w == 2) return codec_kernel<4, 2, MODE, false>;
     return codec_kernel<4, 1, MODE, false>;
   }
-  if (w == 4) return codec_kernel<8, 4, MODE, false>;
-  if (w == 2) return codec_kernel<8, 2, MODE, false>;
+  // (no 16-byte variant for wide codes: its arguments would be copied to
+  // scratch for dynamic indexing)
+  if (w >= 2) return codec_kernel<8, 2, MODE, false>;
   return codec_kernel<8, 1, MODE, false>;
+}
+
+template <int MODE>
+BatchFn pick_batch(int sb, int w) {
+  if (sb == 4) {
+    if (w == 4) return batch_kernel<4, 4, MODE>;
+    if (w == 2) return batch_kernel<4, 2, MODE>;
+    return batch_kernel<4, 1, MODE>;
+  }
+  if (w == 4) return batch_kernel<8, 4, MODE>;
+  if (w == 2) return batch_kernel<8, 2, MODE>;
+  return batch_kernel<8, 1, MODE>;
 }
 
 }  // namespace
 
-int codec_wgs_per_cu(Mode mode) { return mode == kDecode ? 1 : 2; }
+int codec_wgs_per_cu(Mode) { return 2; }
+
+int codec_plain_max_dwords(int sb) { return sb == 8 ? 2 : 4; }
+
+int codec_max_threads(int sb, int dwords_per_lane) {
+  if (dwords_per_lane == 4) return sb == 8 ? 256 : 512;
+  return 1024;
+}
 
 int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, void *stream) {
   KernelFn fn = mode == kEncode ? pick<kEncode>(sb, cfg.dwords_per_lane, cfg.bytewise)
                                 : pick<kDecode>(sb, cfg.dwords_per_lane, cfg.bytewise);
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0,
                      reinterpret_cast<hipStream_t>(stream), p);
+  return (int)hipGetLastError();
+}
+
+int launch_batch(Mode mode, int sb, const BatchGroup &g, uint32_t max_stripes,
+                 const LaunchCfg &cfg, void *stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint32_t prep_threads = 256;
+  const uint32_t prep_grid = (max_stripes + prep_threads - 1) / prep_threads;
+  hipLaunchKernelGGL(batch_prepare_kernel, dim3(prep_grid ? prep_grid : 1), dim3(prep_threads),
+                     0, st, g);
+  int err = (int)hipGetLastError();
+  if (err) return err;
+  BatchFn fn = mode == kEncode ? pick_batch<kEncode>(sb, cfg.dwords_per_lane)
+                               : pick_batch<kDecode>(sb, cfg.dwords_per_lane);
+  hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0, st, g);
   return (int)hipGetLastError();
 }
 

@@ -21,23 +21,32 @@ constexpr int kMaxM = 8;
 // LDS layout: entry e of every table starts at byte e * 256, so a single
 // v_perm_b32 turns (index byte, lane offset byte) into an LDS address.  Each
 // 256-byte entry row holds several tables side by side, each replicated so
-// that lanes of a wave spread over banks.
+// that lanes of a wave spread over banks; 64 KiB in all.
 constexpr uint32_t kRowBytes = 256;
-constexpr uint32_t kApplyRegion = 65536;     // decode apply tables start here
 
 // State width in bytes for a code with m parity symbols.
 inline int state_bytes(int m) { return m <= 4 ? 4 : 8; }
+
+// Kernels address columns with 32-bit offsets: the host hands them blocks
+// of at most this many bytes, splitting longer blocks into independent
+// column ranges (every column is its own codeword).
+constexpr uint64_t kMaxPieceBytes = 1ull << 31;
+
+// Device buffer of zeros that stands in for blocks a kernel does not read,
+// so that every load slot issues a real load (see load_item in codec.hip).
+constexpr uint32_t kZeroPageBytes = 65536;
 
 // Kernel arguments, passed by value (about 2.8 KiB, within the kernarg limit).
 struct CodecParams {
   const uint8_t *data[kMaxN];     // d_j; nullptr = symbol 0, not read
   const uint8_t *par_in[kMaxM];   // decode: parity p_i read back, or nullptr
   uint8_t *out[kMaxM];            // encode: p_i; decode: i-th erased block
-  uint64_t block_bytes;
+  uint64_t block_bytes;           // <= kMaxPieceBytes
   int32_t k;                      // data blocks
   int32_t m;                      // parity symbols (remainder bytes)
   int32_t k_pad;                  // k rounded up to the state width
   int32_t n_out;                  // blocks written
+  const uint8_t *zero_page;       // kZeroPageBytes of zeros on the device
   uint32_t lfsr_basis[16];        // 8 values of T'(2^b), 1 or 2 dwords each
   uint32_t apply_basis[kMaxM][16];// decode: per remainder byte, 8 values
 };
@@ -56,7 +65,56 @@ struct LaunchCfg {
 int launch_codec(Mode mode, int state_bytes, const CodecParams &p,
                  const LaunchCfg &cfg, void *stream);
 
+// ------------------------------------------------------------- batches --
+//
+// A batch group holds stripes whose codes share a state width.  Its columns
+// are cut into tiles of tile_cols bytes (a stripe's last tile may be short);
+// tiles are numbered stripe after stripe.
+
+struct StripeDesc {
+  uint64_t block_bytes;  // <= kMaxPieceBytes
+  uint64_t tile_begin;   // first tile of the stripe
+  uint64_t ptr_off;      // first pointer-table entry: k data, m parity-in, n_out out
+  uint32_t lfsr_set;     // index of the stripe's LFSR basis set
+  uint32_t apply_set;    // decode: index of its apply basis set
+  int32_t k, m, k_pad, n_out;
+};
+
+// A group's arena starts with this header; the regions after it are packed
+// per call and located by the byte offsets below, so one host-to-device copy
+// uploads a whole batch and captured graphs never need new arguments.
+struct BatchHeader {
+  uint64_t total_tiles;
+  uint64_t counter;      // next tile to hand out; cleared by the prepare kernel
+  uint32_t n_stripes;
+  uint32_t reserved;
+  uint64_t off_descs;    // StripeDesc[n_stripes]
+  uint64_t off_ptrs;     // uint64_t device pointers
+  uint64_t off_lfsr;     // 16 dwords per LFSR basis set
+  uint64_t off_apply;    // kMaxM * 16 dwords per apply basis set
+};
+
+struct BatchGroup {            // device pointers
+  uint8_t *arena;              // BatchHeader, then the packed regions
+  uint32_t *tile_stripe;       // tile -> stripe, filled by the prepare kernel
+  const uint8_t *zero_page;    // kZeroPageBytes of zeros
+  uint32_t tile_cols;          // multiple of 16
+};
+
+// kZeroPageBytes of zeros on the current device, allocated and cleared on
+// first use (per device, kept until the process ends); nullptr on error.
+const uint8_t *device_zero_page();
+
+// Enqueues the prepare kernel and the persistent batch kernel for a group
+// (max_stripes bounds the prepare grid).  Returns a hipError_t as int.
+int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint32_t max_stripes,
+                 const LaunchCfg &cfg, void *stream);
+
 // Resident workgroups per CU the kernel is sized for (LDS bound).
 int codec_wgs_per_cu(Mode mode);
+// Largest workgroup a variant is compiled for (register bound).
+int codec_max_threads(int state_bytes, int dwords_per_lane);
+// Widest loads (dwords per lane) of the one-stripe kernel for a state width.
+int codec_plain_max_dwords(int state_bytes);
 
 }  // namespace rsp

@@ -4,8 +4,16 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "gf.h"
 #include "rs_internal.h"
+
+// The opaque code handle of the C ABI.
+struct rs_poly {
+  rsp::Code code;
+  std::mutex mu;
+};
 
 namespace rsp {
 
@@ -15,7 +23,7 @@ int device_cu_count();
 int pointer_alignment(const void *p);
 // Launch shape for one stripe of B-byte blocks whose pointers are all
 // aligned to min_align bytes.
-LaunchCfg default_cfg(Mode mode, uint64_t B, int min_align, int num_cu);
+LaunchCfg default_cfg(Mode mode, int state_bytes, uint64_t B, int min_align, int num_cu);
 // hipError_t -> RS_OK / RS_EDEVICE.
 int hip_status(int err);
 
@@ -23,9 +31,11 @@ int hip_status(int err);
 // list sorted increasingly to sorted_out (capacity kMaxM).
 int validate_erasures(const Code &c, const int *e, int t, unsigned flags, int *sorted_out);
 
+// Kernel arguments for the column range [offset, offset + B) of a stripe.
 void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *const *parity,
-                        uint64_t B, CodecParams *p);
+                        uint64_t offset, uint64_t B, CodecParams *p);
 void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
-                        const int *sorted, int t, uint64_t B, CodecParams *p);
+                        const int *sorted, int t, uint64_t offset, uint64_t B,
+                        CodecParams *p);
 
 }  // namespace rsp
