@@ -53,6 +53,87 @@ def measured_traffic(kernel, src_hash):
     return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
+CALIB_BYTES = 1 << 30       # size of the copy that calibrates the counters
+
+
+def calibrate_copy():
+    """A plain device copy of CALIB_BYTES, run 5 times: the counters of this
+    known-size kernel give the scale of FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    src = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": CALIB_BYTES, "launches": 5}), flush=True)
+
+
+def _counter_means(csv_path, counter):
+    """Mean counter value per kernel name (first 60 chars) from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    sums, counts = {}, {}
+    with open(csv_path) as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] != counter:
+                continue
+            name = row["Kernel_Name"]
+            sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
+            counts[name] = counts.get(name, 0) + 1
+    return {n: (sums[n] / counts[n], counts[n]) for n in sums}
+
+
+def traffic_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path):
+    """Writes the per-launch HBM bytes of the batch kernels: the FETCH_SIZE
+    and WRITE_SIZE means (KiB per dispatch), each scaled so that the
+    calibration copy reads and writes exactly CALIB_BYTES."""
+    def pick(means, key):
+        hits = [(v, n) for name, (v, n) in means.items() if key in name]
+        if not hits:
+            raise SystemExit(f"no kernel matching {key!r}")
+        return max(hits)
+
+    # torch's same-dtype copy_ runs as the HIP runtime's copy kernel
+    cf, _ = pick(_counter_means(cal_fetch_csv, "FETCH_SIZE"), "copyBuffer")
+    cw, _ = pick(_counter_means(cal_write_csv, "WRITE_SIZE"), "copyBuffer")
+    f_scale = CALIB_BYTES / (cf * 1024.0)
+    w_scale = CALIB_BYTES / (cw * 1024.0)
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    kernels = {}
+    for label, key in (("batch_encode", "batch_kernel<4, 4, 0>"),
+                       ("batch_encode", "batch_kernel<4, 2, 0>"),
+                       ("batch_encode", "batch_kernel<4, 1, 0>"),
+                       ("batch_decode", "batch_kernel<4, 4, 1>"),
+                       ("batch_decode", "batch_kernel<4, 2, 1>"),
+                       ("batch_decode", "batch_kernel<4, 1, 1>")):
+        fv = [v for n, (v, c) in fetch.items() if key in n]
+        wv = [v for n, (v, c) in write.items() if key in n]
+        if not fv or not wv:
+            continue
+        fb, wb = fv[0] * 1024.0 * f_scale, wv[0] * 1024.0 * w_scale
+        kernels[label] = {"kernel": key, "fetch_kib_raw": fv[0], "write_kib_raw": wv[0],
+                          "fetch_bytes": round(fb), "write_bytes": round(wb),
+                          "hbm_bytes_per_launch": round(fb + wb)}
+    cmd = "rocprofv3 --pmc {c} -d <out> -o run --output-format csv -- python3 bench.py {a}"
+    rec = {"workload": "rs104_256x1MiB", "kernel_source_hash": kernel_source_hash(),
+           "commands": [cmd.format(c=c, a=a) for c in ("FETCH_SIZE", "WRITE_SIZE") for a in (
+               "--steps 3 --warmup 1 --plain-steps 0 --cpu-sample 0", "--calibrate-copy")] +
+           ["python3 bench.py --traffic-from <FETCH csv> <WRITE csv> <calibration FETCH csv> "
+            "<calibration WRITE csv>"],
+           "note": "counter values are KiB per dispatch; each is scaled by what it reads for "
+                   "the 1 GiB calibration copy (__amd_rocclr_copyBuffer)",
+           "calibration": {"copy_bytes": CALIB_BYTES, "fetch_kib_raw": cf, "write_kib_raw": cw,
+                           "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec), flush=True)
+
+
 def cpu_baseline(host_stripes, erasures, threads):
     """The oracle, unchanged, on a bounded sample: encode then decode of each
     sampled stripe; stripes run in parallel threads (ctypes drops the GIL)."""
@@ -89,7 +170,20 @@ def main():
                     help="stripes the CPU oracle encodes+decodes (0 = skip)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this workload before timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the known-size copy used to scale HBM counters")
+    ap.add_argument("--traffic-from", nargs=4, metavar="CSV",
+                    help="FETCH, WRITE, calibration FETCH, calibration WRITE "
+                         "counter_collection.csv files -> profiles/ traffic JSON")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        traffic_summary(*args.traffic_from,
+                        os.path.join(ROOT, "profiles", "traffic_rs104_256x1MiB.json"))
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
