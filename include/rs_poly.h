@@ -223,6 +223,98 @@ int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide,
 int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes,
                  int count, void *stream, rs_poly_launch_t *best);
 
+/* ------------------------------------------------------------ serving --
+ *
+ * A continuous-batching request engine over the batch API (not in the
+ * paper; it is how the codec is used under load).  Requests are encodes of
+ * caller-resident data and degraded reads (decodes) of caller-resident
+ * stripes.  A scheduler thread admits requests in arrival order while the
+ * HBM budget and a free output buffer allow, groups the admitted ones into
+ * a batch and launches it on one of `streams` streams, so batches formed
+ * while others run overlap on the device.  Outputs (parity for encode,
+ * rebuilt blocks for decode) are allocated from a device pool the engine
+ * owns; they are bit-identical to what rs_poly_encode / rs_poly_decode
+ * produce for the same request alone. */
+
+typedef struct rs_serve rs_serve_t;
+
+typedef struct rs_serve_config {
+    size_t hbm_budget_bytes;  /* bytes admitted requests may charge at once;  *
+                               * also the size of the output pool (> 0)       */
+    int streams;              /* batches in flight at once, 1..8              */
+    int max_batch;            /* most requests per batch, >= 1                */
+    int auto_release;         /* 1: free outputs and budget at completion     */
+} rs_serve_config_t;
+
+typedef struct rs_serve_request {
+    int op;                   /* RS_POLY_OP_ENCODE or RS_POLY_OP_DECODE       */
+    rs_poly_t *code;
+    uint8_t *const *blocks;   /* n device pointers, API order.  Encode reads  *
+                               * 0..k-1 (parity entries ignored); decode reads *
+                               * survivors (erased entries ignored).  Must    *
+                               * stay valid until the request completes.      */
+    size_t block_bytes;       /* > 0                                          */
+    const int *erasures;      /* decode: lost API indices                     */
+    int n_erasures;           /* decode: 1..m                                 */
+    unsigned flags;           /* decode: 0 or RS_POLY_FLAG_ALL_SURVIVORS      */
+    uint64_t user_tag;        /* returned with the completion                 */
+} rs_serve_request_t;
+
+typedef struct rs_serve_completion {
+    uint64_t ticket;
+    uint64_t user_tag;
+    int status;               /* RS_OK or the error of its batch             */
+    int n_out;                /* m (encode) or t (decode)                    */
+    uint8_t *out[RS_POLY_MAX_M]; /* encode: p_0..p_(m-1); decode: blocks in   *
+                               * increasing erased index order; owned by the  *
+                               * engine until released                       */
+    int out_index[RS_POLY_MAX_M]; /* API index of each output block          */
+    size_t charge_bytes;      /* budget held: (k+m)B encode, (k+t)B decode    */
+    double queue_us;          /* submit -> batch launch                       */
+    double latency_us;        /* submit -> completion observed by the engine  */
+} rs_serve_completion_t;
+
+typedef struct rs_serve_stats {
+    uint64_t submitted, completed, batches;
+    uint64_t user_bytes;      /* k*B summed over completed requests           */
+    size_t budget_in_use;     /* now                                          */
+    size_t budget_peak;       /* highest charge held at once                  */
+    int peak_inflight_batches;
+    int pending;              /* submitted, not yet admitted                  */
+} rs_serve_stats_t;
+
+/* Creates the engine on the current device: allocates the output pool and
+ * starts the scheduler thread.  Errors: RS_ENULL, RS_EINVAL, RS_ENOMEM,
+ * RS_EDEVICE. */
+int rs_serve_create(const rs_serve_config_t *cfg, rs_serve_t **out);
+
+/* Queues a request (validated here, as rs_poly_batch_* would) and returns
+ * its ticket.  Non-blocking.  A request whose charge exceeds the whole
+ * budget is rejected with RS_EINVAL. */
+int rs_serve_submit(rs_serve_t *s, const rs_serve_request_t *req, uint64_t *ticket);
+
+/* Replays a request trace from an engine-owned arrival thread: request i is
+ * submitted arrival_us[i] microseconds after the call (non-decreasing
+ * times).  Returns at once; tickets are 1 + the submission count so far. */
+int rs_serve_replay(rs_serve_t *s, const rs_serve_request_t *reqs,
+                    const double *arrival_us, int count);
+
+/* Moves up to max finished requests into out (in completion order); waits
+ * up to timeout_us for the first one (0 = do not wait).  *n_done receives
+ * the count. */
+int rs_serve_poll(rs_serve_t *s, rs_serve_completion_t *out, int max, int *n_done,
+                  int timeout_us);
+
+/* Returns a completed request's outputs to the pool and its charge to the
+ * budget (no-op with auto_release).  Errors: RS_ERANGE (unknown ticket). */
+int rs_serve_release(rs_serve_t *s, uint64_t ticket);
+
+int rs_serve_stats(rs_serve_t *s, rs_serve_stats_t *out);
+
+/* Stops accepting requests, waits for queued and running ones to finish,
+ * stops the threads and frees the pool.  NULL is a no-op. */
+void rs_serve_destroy(rs_serve_t *s);
+
 #ifdef __cplusplus
 }
 #endif

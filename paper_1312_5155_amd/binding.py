@@ -41,6 +41,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1312_5155_amd.build`")
+    try:
+        # When PyTorch provides device memory and streams, load its HIP
+        # runtime first: the library then binds to the same (one) runtime.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, u, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
     pp = ctypes.POINTER(ctypes.c_void_p)
@@ -65,8 +71,53 @@ def load():
     lib.rs_poly_batch_get_launch.argtypes = [vp, i, i, lp]
     lib.rs_poly_batch_set_launch.argtypes = [vp, i, i, lp]
     lib.rs_poly_tune.argtypes = [vp, i, sp, i, vp, lp]
+    rq = ctypes.POINTER(ServeRequest)
+    cp = ctypes.POINTER(ServeCompletion)
+    lib.rs_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
+    lib.rs_serve_submit.argtypes = [vp, rq, ctypes.POINTER(ctypes.c_uint64)]
+    lib.rs_serve_replay.argtypes = [vp, rq, ctypes.POINTER(ctypes.c_double), i]
+    lib.rs_serve_poll.argtypes = [vp, cp, i, ip, i]
+    lib.rs_serve_release.argtypes = [vp, ctypes.c_uint64]
+    lib.rs_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    lib.rs_serve_destroy.argtypes = [vp]
+    lib.rs_serve_destroy.restype = None
     _lib = lib
     return lib
+
+
+class ServeConfig(ctypes.Structure):
+    """rs_serve_config_t."""
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("auto_release", ctypes.c_int)]
+
+
+class ServeRequest(ctypes.Structure):
+    """rs_serve_request_t."""
+    _fields_ = [("op", ctypes.c_int), ("code", ctypes.c_void_p),
+                ("blocks", ctypes.POINTER(ctypes.c_void_p)), ("block_bytes", ctypes.c_size_t),
+                ("erasures", ctypes.POINTER(ctypes.c_int)), ("n_erasures", ctypes.c_int),
+                ("flags", ctypes.c_uint), ("user_tag", ctypes.c_uint64)]
+
+
+class ServeCompletion(ctypes.Structure):
+    """rs_serve_completion_t."""
+    _fields_ = [("ticket", ctypes.c_uint64), ("user_tag", ctypes.c_uint64),
+                ("status", ctypes.c_int), ("n_out", ctypes.c_int),
+                ("out", ctypes.c_void_p * RS_POLY_MAX_M),
+                ("out_index", ctypes.c_int * RS_POLY_MAX_M),
+                ("charge_bytes", ctypes.c_size_t), ("queue_us", ctypes.c_double),
+                ("latency_us", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    """rs_serve_stats_t."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("user_bytes", ctypes.c_uint64),
+                ("budget_in_use", ctypes.c_size_t), ("budget_peak", ctypes.c_size_t),
+                ("peak_inflight_batches", ctypes.c_int), ("pending", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Stripe(ctypes.Structure):
@@ -317,3 +368,75 @@ class Batch:
 
     def tune(self, op, stripes, stream=None):
         return rs_poly_tune(self._b, op, stripes, stream)
+
+
+class RequestArray:
+    """A prepared rs_serve_request_t array.  Entries are dicts with keys op,
+    code, blocks, block_bytes and, for decode, erasures (and flags); tag
+    defaults to the entry's index."""
+
+    def __init__(self, entries):
+        self.count = len(entries)
+        self.arr = (ServeRequest * max(1, self.count))()
+        self._keep = []
+        for i, e in enumerate(entries):
+            bl = _ptr_array(list(e["blocks"]))
+            er = list(e.get("erasures") or [])
+            ea = (ctypes.c_int * max(1, len(er)))(*er)
+            self._keep += [bl, ea]
+            code = e["code"]
+            h = code.handle if isinstance(code, Code) else code
+            self.arr[i] = ServeRequest(e["op"], h, ctypes.cast(bl, ctypes.POINTER(ctypes.c_void_p)),
+                                       e["block_bytes"],
+                                       ctypes.cast(ea, ctypes.POINTER(ctypes.c_int)), len(er),
+                                       e.get("flags", 0), e.get("tag", i))
+
+
+class Serve:
+    """The continuous-batching serving engine (rs_serve_*)."""
+
+    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, auto_release=True):
+        cfg = ServeConfig(hbm_budget_bytes, streams, max_batch, 1 if auto_release else 0)
+        self._s = ctypes.c_void_p()
+        check(load().rs_serve_create(ctypes.byref(cfg), ctypes.byref(self._s)),
+              "rs_serve_create")
+        self._keep = []
+
+    def submit(self, entry):
+        ra = RequestArray([entry])
+        t = ctypes.c_uint64()
+        check(load().rs_serve_submit(self._s, ra.arr, ctypes.byref(t)), "rs_serve_submit")
+        return t.value
+
+    def replay(self, entries, arrival_us):
+        ra = entries if isinstance(entries, RequestArray) else RequestArray(entries)
+        times = (ctypes.c_double * max(1, ra.count))(*arrival_us)
+        self._keep.append((ra, times))
+        check(load().rs_serve_replay(self._s, ra.arr, times, ra.count), "rs_serve_replay")
+
+    def poll(self, max_n=256, timeout_us=0):
+        buf = (ServeCompletion * max_n)()
+        n = ctypes.c_int()
+        check(load().rs_serve_poll(self._s, buf, max_n, ctypes.byref(n), timeout_us),
+              "rs_serve_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def release(self, ticket):
+        check(load().rs_serve_release(self._s, ticket), "rs_serve_release")
+
+    def stats(self):
+        st = ServeStats()
+        check(load().rs_serve_stats(self._s, ctypes.byref(st)), "rs_serve_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._s is not None:
+            load().rs_serve_destroy(self._s)
+            self._s = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

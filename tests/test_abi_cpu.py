@@ -159,3 +159,35 @@ def test_decode_plan_random_patterns(k, m, w, poly):
             _, out = apply_plan_on_cpu(F, k, m, full, er, flags, code)
             for e, v in out.items():
                 assert np.array_equal(v, full[e]), (er, e, flags)
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    # The binding's struct layouts against what a C compiler makes of
+    # include/rs_poly.h.
+    import subprocess
+    src = tmp_path / "sizes.c"
+    src.write_text("""
+#include <stddef.h>
+#include <stdio.h>
+#include "rs_poly.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rs_poly_stripe_t), sizeof(rs_poly_launch_t),
+         sizeof(rs_serve_config_t), sizeof(rs_serve_request_t),
+         sizeof(rs_serve_completion_t), sizeof(rs_serve_stats_t));
+  printf("%zu %zu %zu\\n", offsetof(rs_serve_completion_t, out),
+         offsetof(rs_serve_completion_t, charge_bytes), offsetof(rs_serve_request_t, user_tag));
+  return 0;
+}
+""")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True,
+                           check=True).stdout.split("\n")
+    want = [int(x) for x in lines[0].split()]
+    got = [ctypes.sizeof(t) for t in (B.Stripe, B.Launch, B.ServeConfig, B.ServeRequest,
+                                      B.ServeCompletion, B.ServeStats)]
+    assert got == want
+    offs = [int(x) for x in lines[1].split()]
+    assert offs == [B.ServeCompletion.out.offset, B.ServeCompletion.charge_bytes.offset,
+                    B.ServeRequest.user_tag.offset]

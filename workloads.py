@@ -96,3 +96,29 @@ def device_random_blocks(torch, seed, count, nbytes, device="cuda"):
     gen.manual_seed(seed)
     return torch.randint(0, 256, (count, nbytes), dtype=torch.uint8,
                          device=device, generator=gen)
+
+
+def serving_trace(seed, count, k, m, min_request, max_request, encode_frac, rate_per_s,
+                  n_sets):
+    """Request mix of the serving workload: op (encode with probability
+    encode_frac, else a degraded-read decode), data size S log-uniform in
+    [min_request, max_request] (block size ceil(S/k)), which resident set it
+    uses, 1..m erased blocks for decodes, and Poisson arrival times in
+    microseconds (all zero when rate_per_s is None: a backlog)."""
+    rng = meta_rng(seed)
+    sizes = log_uniform_sizes(rng, count, min_request, max_request)
+    ops = (rng.random(count) >= encode_frac).astype(int)   # 0 encode, 1 decode
+    sets = rng.integers(0, n_sets, size=count)
+    out = []
+    for i in range(count):
+        s = int(sizes[i])
+        er = []
+        if ops[i] == 1:
+            er = random_erasures(rng, k + m, int(rng.integers(1, m + 1)))
+        out.append({"op": int(ops[i]), "data_bytes": s, "block_bytes": -(-s // k),
+                    "set": int(sets[i]), "erasures": er})
+    if rate_per_s is None:
+        times = np.zeros(count)
+    else:
+        times = poisson_arrivals(rng, rate_per_s, count) * 1e6
+    return out, times
