@@ -134,6 +134,83 @@ def traffic_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path
     print(json.dumps(rec), flush=True)
 
 
+def serving_run(srv, sets, trace, times):
+    """Replays one trace and returns (makespan s, latencies us, user bytes)."""
+    import numpy as np
+
+    from paper_1312_5155_amd import binding as B
+    reqs = B.RequestArray(sets.entries(trace))     # marshalled before timing
+    before = srv.stats()
+    t0 = time.perf_counter()
+    srv.replay(reqs, times)
+    done = []
+    while len(done) < reqs.count:
+        done += srv.poll(4096, timeout_us=50000)
+    span = time.perf_counter() - t0
+    if any(c.status != 0 for c in done):
+        raise SystemExit("a serving request failed")
+    lat = np.array([c.latency_us for c in done])
+    user = sum(r["data_bytes"] for r in trace)
+    after = srv.stats()
+    serving_run.last = {k: round(after[k] - before[k], 1) for k in
+                        ("batches", "launch_host_us", "batch_device_us", "admit_host_us")}
+    serving_run.last["span_us"] = round(span * 1e6, 1)
+    return span, lat, user
+
+
+def serving(fractions, count):
+    """Serving workload: RS(10,4), requests of log-uniform 64 KiB-64 MiB of
+    data (70% encodes, 30% degraded reads with 1-4 erasures) on resident
+    stripes, admitted under a 64 GiB HBM budget.  Capacity is measured with a
+    backlog (every request arriving at t=0); then a Poisson trace at each
+    fraction of it.  GB/s counts user data bytes (the request sizes)."""
+    import numpy as np
+
+    import workloads
+    from paper_1312_5155_amd import binding as B
+    from paper_1312_5155_amd.serving import ResidentSets
+
+    cfg = workloads.CONFIGS["serving_rs104"]
+    seed = workloads.meta_seed(cfg["index"])
+    k, m = cfg["k"], cfg["m"]
+    n_sets = 24
+    code = B.Code(k, m)
+    sets = ResidentSets(code, n_sets, -(-cfg["max_request"] // k),
+                        seed=workloads.data_seed(cfg["index"]))
+    srv = B.Serve(cfg["hbm_budget"], streams=4, max_batch=64, auto_release=True,
+                  max_block_bytes=-(-cfg["max_request"] // k))
+
+    def trace(s, rate):
+        return workloads.serving_trace(s, count, k, m, cfg["min_request"], cfg["max_request"],
+                                       cfg["encode_frac"], rate, n_sets)
+
+    tr, tm = trace(seed, None)
+    serving_run(srv, sets, tr[:2000], tm[:2000])        # warm-up (graphs, plans)
+    # capacity: the better of two backlog runs (every request at t = 0)
+    runs = [serving_run(srv, sets, tr, tm) for _ in range(2)]
+    span, lat, user = min(runs, key=lambda r: r[0])
+    cap_rps = count / span
+    out = {"capacity": {"req_s": round(cap_rps), "gbs": round(user / span / 1e9, 1),
+                        "p50_us": round(float(np.percentile(lat, 50)), 1),
+                        "p99_us": round(float(np.percentile(lat, 99)), 1),
+                        **serving_run.last},
+           "points": []}
+    for i, f in enumerate(fractions):
+        tr, tm = trace(seed + 1 + i, f * cap_rps)
+        span, lat, user = serving_run(srv, sets, tr, tm)
+        out["points"].append({"load": f, "offered_req_s": round(f * cap_rps),
+                              "gbs": round(user / span / 1e9, 1),
+                              "p50_us": round(float(np.percentile(lat, 50)), 1),
+                              "p99_us": round(float(np.percentile(lat, 99)), 1),
+                              **serving_run.last})
+    st = srv.stats()
+    out.update({"requests_per_point": count, "streams": 4, "max_batch": 64,
+                "hbm_budget_bytes": cfg["hbm_budget"], "budget_peak_bytes": st["budget_peak"],
+                "peak_inflight_batches": st["peak_inflight_batches"]})
+    srv.close()
+    return out
+
+
 def cpu_baseline(host_stripes, erasures, threads):
     """The oracle, unchanged, on a bounded sample: encode then decode of each
     sampled stripe; stripes run in parallel threads (ctypes drops the GIL)."""
@@ -170,6 +247,10 @@ def main():
                     help="stripes the CPU oracle encodes+decodes (0 = skip)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this workload before timing")
+    ap.add_argument("--serving-requests", type=int, default=10000,
+                    help="requests per serving load point (0 = skip serving)")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="only the serving workload, at 0.1..1.2 of capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the known-size copy used to scale HBM counters")
     ap.add_argument("--traffic-from", nargs=4, metavar="CSV",
@@ -183,6 +264,10 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.serving_sweep:
+        res = serving([0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.2], max(1, args.serving_requests))
+        print(json.dumps({"workload": "serving_rs104", **res}), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -303,6 +388,12 @@ def main():
                "sample": f"{n} of the {STRIPES} stripes, encode + decode each "
                          f"({secs:.1f} s wall on {threads} threads)"}
 
+    serve = None
+    if args.serving_requests > 0:
+        del buf
+        torch.cuda.empty_cache()
+        serve = serving([0.8], args.serving_requests)
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -317,6 +408,7 @@ def main():
         "launch": {"encode": batch.get_launch(B.RS_POLY_OP_ENCODE, 0).as_dict(),
                    "decode": batch.get_launch(B.RS_POLY_OP_DECODE, 0).as_dict()},
         "plain": plain,
+        "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_source_hash": src_hash,

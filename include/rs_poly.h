@@ -168,7 +168,9 @@ typedef struct rs_poly_launch {
     int bytes_per_lane;   /* columns per lane per block: 4, 8 or 16            */
     int threads;          /* workgroup size: 256, 512 or 1024; at 16 bytes per *
                            * lane at most 512 (m <= 4) or 256 (m > 4)          */
-    int tile_bytes;       /* columns per tile: a multiple of 16, >= 4096       */
+    int tile_bytes;       /* most columns per tile: a multiple of 16, >= 4096; *
+                           * calls with few columns use smaller tiles so that  *
+                           * every workgroup gets work                         */
     int wgs_per_cu;       /* persistent workgroups per CU: 1 or 2              */
 } rs_poly_launch_t;
 
@@ -203,6 +205,14 @@ int rs_poly_batch_encode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
  * RS_EDEVICE. */
 int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
                          int count, void *stream);
+
+/* Pre-sizes the object's device descriptor buffers, tile map and pinned
+ * staging for calls of up to max_stripes stripes of up to max_block_bytes
+ * each (any codes), so such calls never allocate.  Larger calls still work:
+ * buffers then grow, and replaced buffers are kept until rs_poly_batch_free
+ * (no device-wide synchronization).  Errors: RS_ENULL, RS_EINVAL,
+ * RS_ENOMEM. */
+int rs_poly_batch_reserve(rs_poly_batch_t *b, int max_stripes, size_t max_block_bytes);
 
 /* Reads or sets the launch shape used for (op, state width), where wide = 0
  * selects codes with m <= 4 and wide = 1 codes with 4 < m <= 8.  Shapes are
@@ -244,6 +254,8 @@ typedef struct rs_serve_config {
     int streams;              /* batches in flight at once, 1..8              */
     int max_batch;            /* most requests per batch, >= 1                */
     int auto_release;         /* 1: free outputs and budget at completion     */
+    size_t max_block_bytes;   /* largest block_bytes accepted (0 = any); the  *
+                               * batch buffers are reserved for it up front   */
 } rs_serve_config_t;
 
 typedef struct rs_serve_request {
@@ -281,6 +293,11 @@ typedef struct rs_serve_stats {
     size_t budget_peak;       /* highest charge held at once                  */
     int peak_inflight_batches;
     int pending;              /* submitted, not yet admitted                  */
+    double launch_host_us;    /* host time forming and enqueuing batches      */
+    double batch_device_us;   /* summed device time of batches, from their    *
+                               * first command to their completion event      */
+    double admit_host_us;     /* host time reaping finished batches and       *
+                               * admitting requests                           */
 } rs_serve_stats_t;
 
 /* Creates the engine on the current device: allocates the output pool and

@@ -68,6 +68,7 @@ def load():
     lib.rs_poly_batch_free.restype = None
     lib.rs_poly_batch_encode.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_decode.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_batch_reserve.argtypes = [vp, i, sz]
     lib.rs_poly_batch_get_launch.argtypes = [vp, i, i, lp]
     lib.rs_poly_batch_set_launch.argtypes = [vp, i, i, lp]
     lib.rs_poly_tune.argtypes = [vp, i, sp, i, vp, lp]
@@ -88,7 +89,8 @@ def load():
 class ServeConfig(ctypes.Structure):
     """rs_serve_config_t."""
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int),
-                ("max_batch", ctypes.c_int), ("auto_release", ctypes.c_int)]
+                ("max_batch", ctypes.c_int), ("auto_release", ctypes.c_int),
+                ("max_block_bytes", ctypes.c_size_t)]
 
 
 class ServeRequest(ctypes.Structure):
@@ -114,7 +116,9 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("user_bytes", ctypes.c_uint64),
                 ("budget_in_use", ctypes.c_size_t), ("budget_peak", ctypes.c_size_t),
-                ("peak_inflight_batches", ctypes.c_int), ("pending", ctypes.c_int)]
+                ("peak_inflight_batches", ctypes.c_int), ("pending", ctypes.c_int),
+                ("launch_host_us", ctypes.c_double), ("batch_device_us", ctypes.c_double),
+                ("admit_host_us", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -360,6 +364,10 @@ class Batch:
     def decode(self, stripes, stream=None):
         return rs_poly_batch_decode(self._b, stripes, stream)
 
+    def reserve(self, max_stripes, max_block_bytes):
+        return check(load().rs_poly_batch_reserve(self._b, max_stripes, max_block_bytes),
+                     "rs_poly_batch_reserve")
+
     def get_launch(self, op, wide=0):
         return rs_poly_batch_get_launch(self._b, op, wide)
 
@@ -395,8 +403,10 @@ class RequestArray:
 class Serve:
     """The continuous-batching serving engine (rs_serve_*)."""
 
-    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, auto_release=True):
-        cfg = ServeConfig(hbm_budget_bytes, streams, max_batch, 1 if auto_release else 0)
+    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, auto_release=True,
+                 max_block_bytes=0):
+        cfg = ServeConfig(hbm_budget_bytes, streams, max_batch, 1 if auto_release else 0,
+                          max_block_bytes)
         self._s = ctypes.c_void_p()
         check(load().rs_serve_create(ctypes.byref(cfg), ctypes.byref(self._s)),
               "rs_serve_create")
@@ -415,11 +425,20 @@ class Serve:
         check(load().rs_serve_replay(self._s, ra.arr, times, ra.count), "rs_serve_replay")
 
     def poll(self, max_n=256, timeout_us=0):
-        buf = (ServeCompletion * max_n)()
+        """Up to max_n completions (copies), waiting up to timeout_us."""
+        if getattr(self, "_pbuf_n", 0) < max_n:
+            self._pbuf = (ServeCompletion * max_n)()
+            self._pbuf_n = max_n
+        buf = self._pbuf
         n = ctypes.c_int()
         check(load().rs_serve_poll(self._s, buf, max_n, ctypes.byref(n), timeout_us),
               "rs_serve_poll")
-        return [buf[i] for i in range(n.value)]
+        out = []
+        for i in range(n.value):
+            c = ServeCompletion()
+            ctypes.pointer(c)[0] = buf[i]
+            out.append(c)
+        return out
 
     def release(self, ticket):
         check(load().rs_serve_release(self._s, ticket), "rs_serve_release")

@@ -37,7 +37,7 @@ struct GroupBuf {
   uint64_t version = 0;           // bumped when device buffers move
 };
 
-using GraphKey = std::tuple<int, int, int, int, int, int, uint64_t>;
+using GraphKey = std::tuple<int, int, int, int, int, uint64_t>;
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
@@ -82,16 +82,26 @@ struct rs_poly_batch {
   std::string arch;
   hipStream_t capture = nullptr;
   GroupBuf groups[kWidths];
-  uint8_t *staging = nullptr;     // pinned host memory, both groups
-  size_t staging_bytes = 0;
-  hipEvent_t staging_free = nullptr;
-  bool staging_pending = false;
+  // Two pinned staging buffers used in turn; each event marks the end of
+  // the upload from that buffer, so the host rarely waits to refill one.
+  uint8_t *staging[2] = {nullptr, nullptr};
+  size_t staging_bytes[2] = {0, 0};
+  hipEvent_t staging_free[2] = {nullptr, nullptr};
+  bool staging_pending[2] = {false, false};
+  int staging_next = 0;
+  // Marks the end of the last call's kernels: a call on another stream
+  // waits for it (on the device) before its upload overwrites the arena.
+  hipEvent_t last_done = nullptr;
+  bool last_done_valid = false;
   rs_poly_launch_t launch[kOps][kWidths];
   std::map<GraphKey, GraphEntry> graphs;
+  // Device and pinned buffers replaced by larger ones; kernels queued earlier
+  // may still read them, so they are freed with the object.
+  std::vector<void *> retired_dev, retired_host;
 
   ~rs_poly_batch();
   void drop_graphs();
-  int ensure_staging(size_t bytes);
+  int ensure_staging(int i, size_t bytes);
   int ensure_group(int wide, size_t arena_bytes, uint64_t tiles, uint32_t stripes);
   int graph_for(int op, int wide, const rs_poly_launch_t &cfg, hipGraphExec_t *out);
   int run(int op, const rs_poly_stripe_t *stripes, int count, void *stream);
@@ -106,31 +116,38 @@ void rs_poly_batch::drop_graphs() {
 }
 
 rs_poly_batch::~rs_poly_batch() {
-  if (staging_pending && staging_free) (void)hipEventSynchronize(staging_free);
+  for (int i = 0; i < 2; ++i)
+    if (staging_pending[i]) (void)hipEventSynchronize(staging_free[i]);
   drop_graphs();
   for (auto &g : groups) {
     if (g.arena) (void)hipFree(g.arena);
     if (g.tile_stripe) (void)hipFree(g.tile_stripe);
   }
-  if (staging) (void)hipHostFree(staging);
-  if (staging_free) (void)hipEventDestroy(staging_free);
+  for (int i = 0; i < 2; ++i) {
+    if (staging[i]) (void)hipHostFree(staging[i]);
+    if (staging_free[i]) (void)hipEventDestroy(staging_free[i]);
+  }
+  for (void *p : retired_dev) (void)hipFree(p);
+  for (void *p : retired_host) (void)hipHostFree(p);
+  if (last_done) (void)hipEventDestroy(last_done);
   if (capture) (void)hipStreamDestroy(capture);
 }
 
-int rs_poly_batch::ensure_staging(size_t bytes) {
-  if (bytes <= staging_bytes) return RS_OK;
-  if (staging_pending) {
-    if (hipEventSynchronize(staging_free) != hipSuccess) return RS_EDEVICE;
-    staging_pending = false;
+// Makes staging buffer i hold at least `bytes` and be free to overwrite.
+int rs_poly_batch::ensure_staging(int i, size_t bytes) {
+  if (staging_pending[i]) {
+    if (hipEventSynchronize(staging_free[i]) != hipSuccess) return RS_EDEVICE;
+    staging_pending[i] = false;
   }
-  if (staging) (void)hipHostFree(staging);
-  staging = nullptr;
-  staging_bytes = 0;
+  if (bytes <= staging_bytes[i]) return RS_OK;
+  if (staging[i]) retired_host.push_back(staging[i]);
+  staging[i] = nullptr;
+  staging_bytes[i] = 0;
   const size_t want = align_up(bytes + bytes / 2, 1 << 16);
-  if (hipHostMalloc(reinterpret_cast<void **>(&staging), want, hipHostMallocDefault) !=
+  if (hipHostMalloc(reinterpret_cast<void **>(&staging[i]), want, hipHostMallocDefault) !=
       hipSuccess)
     return RS_ENOMEM;
-  staging_bytes = want;
+  staging_bytes[i] = want;
   return RS_OK;
 }
 
@@ -139,13 +156,13 @@ int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
   GroupBuf &g = groups[wide];
   if (arena_bytes <= g.arena_bytes && tiles <= g.tile_cap && stripes <= g.stripe_cap)
     return RS_OK;
-  // Buffers move: kernels queued earlier may still use them.
-  if (hipDeviceSynchronize() != hipSuccess) return RS_EDEVICE;
+  // Buffers move; kernels queued earlier may still read the old ones, which
+  // are retired rather than freed (no device-wide synchronization).
   const size_t new_arena = std::max(g.arena_bytes, align_up(arena_bytes + arena_bytes / 2, 4096));
   const uint64_t new_tiles = std::max<uint64_t>(g.tile_cap, tiles + tiles / 2 + 64);
   const uint32_t new_stripes = std::max<uint32_t>(g.stripe_cap, stripes + stripes / 2 + 16);
-  if (g.arena) (void)hipFree(g.arena);
-  if (g.tile_stripe) (void)hipFree(g.tile_stripe);
+  if (g.arena) retired_dev.push_back(g.arena);
+  if (g.tile_stripe) retired_dev.push_back(g.tile_stripe);
   g.arena = nullptr;
   g.tile_stripe = nullptr;
   g.arena_bytes = g.tile_cap = g.stripe_cap = 0;
@@ -173,8 +190,7 @@ int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
 int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
                              hipGraphExec_t *out) {
   GroupBuf &gb = groups[wide];
-  const GraphKey key{op, wide, cfg.bytes_per_lane, cfg.threads, cfg.tile_bytes, cfg.wgs_per_cu,
-                     gb.version};
+  const GraphKey key{op, wide, cfg.bytes_per_lane, cfg.threads, cfg.wgs_per_cu, gb.version};
   auto it = graphs.find(key);
   if (it != graphs.end()) {
     *out = it->second.exec;
@@ -182,7 +198,7 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
   }
   const uint8_t *zp = device_zero_page();
   if (!zp) return RS_EDEVICE;
-  BatchGroup g{gb.arena, gb.tile_stripe, zp, (uint32_t)cfg.tile_bytes};
+  BatchGroup g{gb.arena, gb.tile_stripe, zp};
   LaunchCfg lc{};
   lc.dwords_per_lane = cfg.bytes_per_lane / 4;
   lc.threads = cfg.threads;
@@ -192,7 +208,7 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
   if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return RS_EDEVICE;
   const int lerr = launch_batch(op == RS_POLY_OP_DECODE ? kDecode : kEncode, wide ? 8 : 4, g,
-                                gb.stripe_cap, lc, capture);
+                                gb.tile_cap, lc, capture);
   const hipError_t cerr = hipStreamEndCapture(capture, &e.graph);
   if (lerr != 0 || cerr != hipSuccess) {
     if (e.graph) (void)hipGraphDestroy(e.graph);
@@ -220,6 +236,7 @@ struct GroupPlan {
   std::unordered_map<const DecodePlan *, uint32_t> apply_index;
   std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
   uint64_t tiles = 0;
+  uint32_t tile_cols = 0;
   uint64_t bytes = 0;   // user bytes (k * B summed), for tuning choices
 
   size_t layout(size_t *o_descs, size_t *o_ptrs, size_t *o_lfsr, size_t *o_apply) const {
@@ -342,7 +359,15 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   for (int w = 0; w < kWidths; ++w) {
     GroupPlan &gp = plan[w];
     if (gp.descs.empty()) continue;
-    const uint64_t tc = (uint64_t)launch[op][w].tile_bytes;
+    // Tiles of at most the configured size, smaller when the batch is
+    // small, so that every persistent workgroup gets about two tiles.
+    const rs_poly_launch_t &lc = launch[op][w];
+    uint64_t cols = 0;
+    for (auto &d : gp.descs) cols += d.block_bytes;
+    const uint64_t want = cols / (2ull * num_cu * lc.wgs_per_cu);
+    uint64_t tc = std::min<uint64_t>((uint64_t)lc.tile_bytes, std::max<uint64_t>(4096, want));
+    tc = tc / 16 * 16;
+    gp.tile_cols = (uint32_t)tc;
     uint64_t t = 0;
     for (auto &d : gp.descs) {
       d.tile_begin = t;
@@ -361,21 +386,20 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     const int rc = ensure_group(w, upload_len[w], plan[w].tiles, (uint32_t)plan[w].descs.size());
     if (rc != RS_OK) return rc;
   }
-  int rc = ensure_staging(total_upload);
+  const int si = staging_next;
+  staging_next ^= 1;
+  int rc = ensure_staging(si, total_upload);
   if (rc != RS_OK) return rc;
-  if (staging_pending) {
-    if (hipEventSynchronize(staging_free) != hipSuccess) return RS_EDEVICE;
-    staging_pending = false;
-  }
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   for (int w = 0; w < kWidths; ++w) {
     GroupPlan &gp = plan[w];
     if (gp.descs.empty()) continue;
-    uint8_t *h = staging + upload_at[w];
+    uint8_t *h = staging[si] + upload_at[w];
     BatchHeader hdr{};
     hdr.total_tiles = gp.tiles;
     hdr.n_stripes = (uint32_t)gp.descs.size();
+    hdr.tile_cols = gp.tile_cols;
     hdr.off_descs = offs[w][0];
     hdr.off_ptrs = offs[w][1];
     hdr.off_lfsr = offs[w][2];
@@ -386,16 +410,27 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     memcpy(h + offs[w][2], gp.lfsr.data(), gp.lfsr.size() * sizeof(uint32_t));
     if (!gp.apply.empty())
       memcpy(h + offs[w][3], gp.apply.data(), gp.apply.size() * sizeof(uint32_t));
-    if (hipMemcpyAsync(groups[w].arena, h, upload_len[w], hipMemcpyHostToDevice, st) !=
-        hipSuccess)
+  }
+  // The arena may still be read by the previous call's kernels if that call
+  // went to another stream.
+  if (last_done_valid && hipStreamWaitEvent(st, last_done, 0) != hipSuccess) return RS_EDEVICE;
+  for (int w = 0; w < kWidths; ++w) {
+    if (plan[w].descs.empty()) continue;
+    if (hipMemcpyAsync(groups[w].arena, staging[si] + upload_at[w], upload_len[w],
+                       hipMemcpyHostToDevice, st) != hipSuccess)
       return RS_EDEVICE;
+  }
+  if (hipEventRecord(staging_free[si], st) != hipSuccess) return RS_EDEVICE;
+  staging_pending[si] = true;
+  for (int w = 0; w < kWidths; ++w) {
+    if (plan[w].descs.empty()) continue;
     hipGraphExec_t exec;
     rc = graph_for(op, w, launch[op][w], &exec);
     if (rc != RS_OK) return rc;
     if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
   }
-  if (hipEventRecord(staging_free, st) != hipSuccess) return RS_EDEVICE;
-  staging_pending = true;
+  if (hipEventRecord(last_done, st) != hipSuccess) return RS_EDEVICE;
+  last_done_valid = true;
   return RS_OK;
 }
 
@@ -447,6 +482,30 @@ void cache_store(const char *path, const std::string &key, const rs_poly_launch_
 
 extern "C" {
 
+int rs_poly_batch_reserve(rs_poly_batch_t *b, int max_stripes, size_t max_block_bytes) {
+  if (!b) return RS_ENULL;
+  if (max_stripes < 1 || max_block_bytes == 0) return RS_EINVAL;
+  std::lock_guard<std::mutex> lock(b->mu);
+  const uint64_t pieces = (max_block_bytes + kMaxPieceBytes - 1) / kMaxPieceBytes;
+  const uint64_t descs = (uint64_t)max_stripes * pieces;
+  const uint64_t piece = std::min<uint64_t>(max_block_bytes, kMaxPieceBytes);
+  const uint64_t tiles = descs * ((piece + 4095) / 4096);   // smallest tile: 4 KiB
+  size_t arena = align_up(sizeof(BatchHeader), 256);
+  arena = align_up(arena + descs * sizeof(StripeDesc), 256);
+  arena = align_up(arena + descs * (kMaxN + kMaxM) * sizeof(uint64_t), 256);
+  arena = align_up(arena + (uint64_t)max_stripes * 16 * sizeof(uint32_t), 256);
+  arena = align_up(arena + (uint64_t)max_stripes * kMaxM * 16 * sizeof(uint32_t), 256);
+  for (int w = 0; w < kWidths; ++w) {
+    const int rc = b->ensure_group(w, arena, tiles, (uint32_t)descs);
+    if (rc != RS_OK) return rc;
+  }
+  for (int i = 0; i < 2; ++i) {
+    const int rc = b->ensure_staging(i, 2 * arena);
+    if (rc != RS_OK) return rc;
+  }
+  return RS_OK;
+}
+
 int rs_poly_batch_create(rs_poly_batch_t **out) {
   if (!out) return RS_ENULL;
   *out = nullptr;
@@ -458,7 +517,9 @@ int rs_poly_batch_create(rs_poly_batch_t **out) {
   if (hipGetDevice(&b->device) != hipSuccess ||
       hipGetDeviceProperties(&prop, b->device) != hipSuccess ||
       hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->staging_free, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&b->staging_free[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->staging_free[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->last_done, hipEventDisableTiming) != hipSuccess) {
     delete b;
     return RS_EDEVICE;
   }

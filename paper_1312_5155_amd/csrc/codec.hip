@@ -558,18 +558,25 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-// Fills the tile -> stripe map of a batch group and clears its tile
-// counter; runs before the persistent kernel in the same graph.
+// Fills the tile -> stripe map of a batch group (one thread per tile, a
+// binary search over the stripes' first tiles) and clears the tile counter;
+// runs before the persistent kernel in the same graph.  The grid covers the
+// group's tile capacity; threads past the batch's tiles only exit.
 __global__ void batch_prepare_kernel(BatchGroup g) {
   BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
   const StripeDesc *descs = reinterpret_cast<const StripeDesc *>(g.arena + hdr->off_descs);
-  const uint32_t n = hdr->n_stripes;
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) hdr->counter = 0;
-  if (s >= n) return;
-  const uint64_t t0 = descs[s].tile_begin;
-  const uint64_t t1 = s + 1 < n ? descs[s + 1].tile_begin : hdr->total_tiles;
-  for (uint64_t t = t0; t < t1; ++t) g.tile_stripe[t] = s;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) hdr->counter = 0;
+  if (t >= hdr->total_tiles) return;
+  uint32_t lo = 0, hi = hdr->n_stripes - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (descs[mid].tile_begin <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  g.tile_stripe[t] = lo;
 }
 
 // Persistent kernel over every tile of a batch group.  Each workgroup takes
@@ -592,7 +599,7 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
   const uint32_t *apply_sets = reinterpret_cast<const uint32_t *>(g.arena + chdr->off_apply);
   const_as<uint32_t> tile_stripe = as_const(g.tile_stripe);
   unsigned long long *counter = reinterpret_cast<unsigned long long *>(&hdr->counter);
-  const uint32_t tile_cols = g.tile_cols;
+  const uint32_t tile_cols = chdr->tile_cols;
   const uint32_t loff = lfsr_lane_offset<M, MODE>(), aoff = apply_lane_offset<M>();
   uint32_t staged_lfsr = ~0u, staged_apply = ~0u;
 
@@ -676,11 +683,11 @@ int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, 
   return (int)hipGetLastError();
 }
 
-int launch_batch(Mode mode, int sb, const BatchGroup &g, uint32_t max_stripes,
+int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
                  const LaunchCfg &cfg, void *stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const uint32_t prep_threads = 256;
-  const uint32_t prep_grid = (max_stripes + prep_threads - 1) / prep_threads;
+  const uint32_t prep_grid = (uint32_t)((max_tiles + prep_threads - 1) / prep_threads);
   hipLaunchKernelGGL(batch_prepare_kernel, dim3(prep_grid ? prep_grid : 1), dim3(prep_threads),
                      0, st, g);
   int err = (int)hipGetLastError();

@@ -87,7 +87,7 @@ struct BatchHeader {
   uint64_t total_tiles;
   uint64_t counter;      // next tile to hand out; cleared by the prepare kernel
   uint32_t n_stripes;
-  uint32_t reserved;
+  uint32_t tile_cols;    // columns per tile for this call, multiple of 16
   uint64_t off_descs;    // StripeDesc[n_stripes]
   uint64_t off_ptrs;     // uint64_t device pointers
   uint64_t off_lfsr;     // 16 dwords per LFSR basis set
@@ -98,7 +98,6 @@ struct BatchGroup {            // device pointers
   uint8_t *arena;              // BatchHeader, then the packed regions
   uint32_t *tile_stripe;       // tile -> stripe, filled by the prepare kernel
   const uint8_t *zero_page;    // kZeroPageBytes of zeros
-  uint32_t tile_cols;          // multiple of 16
 };
 
 // kZeroPageBytes of zeros on the current device, allocated and cleared on
@@ -106,8 +105,9 @@ struct BatchGroup {            // device pointers
 const uint8_t *device_zero_page();
 
 // Enqueues the prepare kernel and the persistent batch kernel for a group
-// (max_stripes bounds the prepare grid).  Returns a hipError_t as int.
-int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint32_t max_stripes,
+// (max_tiles, the tile-map capacity, sizes the prepare grid).  Returns a
+// hipError_t as int.
+int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint64_t max_tiles,
                  const LaunchCfg &cfg, void *stream);
 
 // Resident workgroups per CU the kernel is sized for (LDS bound).

@@ -31,52 +31,68 @@ double us_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::micro>(b - a).count();
 }
 
-// First-fit allocator over one device allocation, 256-byte granularity.
+// Ring allocator over one device allocation, 256-byte granularity.
+// Outputs are allocated in admission order and freed roughly in completion
+// order, so allocation takes the space after the newest live block and a
+// free advances the tail over blocks already released: O(1) amortized, with
+// no free-list scans under the engine lock.
 class DevicePool {
  public:
   int init(size_t bytes) {
     size_ = (bytes + 255) / 256 * 256;
     if (hipMalloc(reinterpret_cast<void **>(&base_), size_) != hipSuccess) return RS_ENOMEM;
-    free_[0] = size_;
     return RS_OK;
   }
   ~DevicePool() {
     if (base_) (void)hipFree(base_);
   }
-  // Returns the offset, or SIZE_MAX if no hole is large enough.
+  // Returns the offset, or SIZE_MAX if the ring has no room now.
   size_t alloc(size_t bytes) {
     bytes = (bytes + 255) / 256 * 256;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      const size_t off = it->first, left = it->second - bytes;
-      free_.erase(it);
-      if (left) free_[off + bytes] = left;
-      return off;
+    if (bytes > size_) return SIZE_MAX;
+    size_t off;
+    if (live_.empty()) {
+      head_ = tail_ = 0;
+      off = 0;
+    } else if (head_ >= tail_) {
+      // free space: [head, size) and [0, tail)
+      if (size_ - head_ >= bytes)
+        off = head_;
+      else if (tail_ > bytes)   // wrap; strict so head never meets tail
+        off = 0;
+      else
+        return SIZE_MAX;
+    } else {
+      if (tail_ - head_ > bytes)
+        off = head_;
+      else
+        return SIZE_MAX;
     }
-    return SIZE_MAX;
+    head_ = off + bytes;
+    live_.push_back({off, bytes, false});
+    return off;
   }
   void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) / 256 * 256;
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + bytes == next->first) {
-      bytes += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += bytes;
-        return;
+    (void)bytes;
+    for (auto it = live_.begin(); it != live_.end(); ++it)
+      if (it->off == off && !it->freed) {
+        it->freed = true;
+        break;
       }
-    }
-    free_[off] = bytes;
+    while (!live_.empty() && live_.front().freed) live_.pop_front();
+    if (!live_.empty()) tail_ = live_.front().off;
   }
   uint8_t *base() const { return base_; }
 
  private:
+  struct Block {
+    size_t off, bytes;
+    bool freed;
+  };
   uint8_t *base_ = nullptr;
   size_t size_ = 0;
-  std::map<size_t, size_t> free_;   // offset -> length
+  size_t head_ = 0, tail_ = 0;   // next allocation / oldest live block
+  std::deque<Block> live_;       // in allocation order
 };
 
 struct Request {
@@ -93,7 +109,9 @@ struct Request {
 };
 
 struct Slot {
+  uint64_t seq = 0;             // launch order of the batch it holds
   hipStream_t stream = nullptr;
+  hipEvent_t start = nullptr;   // timing: before the batch's first command
   hipEvent_t done = nullptr;
   rs_poly_batch_t *batch = nullptr;
   std::vector<Request *> reqs;
@@ -123,6 +141,7 @@ struct rs_serve {
   rs_serve_stats_t stats{};
   bool stopping = false;
   int inflight = 0;
+  uint64_t launch_seq = 0;
   std::thread scheduler;
   std::vector<std::thread> replayers;
 
@@ -141,6 +160,7 @@ int rs_serve::validate(const rs_serve_request_t &r, Request *q) {
   if (!r.code || !r.blocks) return RS_ENULL;
   if (r.op != RS_POLY_OP_ENCODE && r.op != RS_POLY_OP_DECODE) return RS_EINVAL;
   if (r.block_bytes == 0) return RS_EINVAL;
+  if (cfg.max_block_bytes && r.block_bytes > cfg.max_block_bytes) return RS_EINVAL;
   Code &c = r.code->code;
   const int k = c.k(), m = c.m(), n = c.n();
   auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
@@ -207,7 +227,10 @@ bool rs_serve::reap() {
     const hipError_t e = hipEventQuery(s.done);
     if (e == hipErrorNotReady) continue;
     const Clock::time_point now = Clock::now();
+    float dev_ms = 0;
+    if (e == hipSuccess && hipEventElapsedTime(&dev_ms, s.start, s.done) != hipSuccess) dev_ms = 0;
     std::lock_guard<std::mutex> lock(mu);
+    stats.batch_device_us += 1e3 * dev_ms;
     for (Request *q : s.reqs) {
       q->done = now;
       if (e != hipSuccess) q->status = RS_EDEVICE;
@@ -287,7 +310,9 @@ bool rs_serve::launch() {
   }
   const Clock::time_point now = Clock::now();
   int rc = RS_OK;
-  if (!enc.empty()) rc = rs_poly_batch_encode(slot->batch, enc.data(), (int)enc.size(), slot->stream);
+  if (hipEventRecord(slot->start, slot->stream) != hipSuccess) rc = RS_EDEVICE;
+  if (rc == RS_OK && !enc.empty())
+    rc = rs_poly_batch_encode(slot->batch, enc.data(), (int)enc.size(), slot->stream);
   if (rc == RS_OK && !dec.empty())
     rc = rs_poly_batch_decode(slot->batch, dec.data(), (int)dec.size(), slot->stream);
   if (rc == RS_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) rc = RS_EDEVICE;
@@ -297,7 +322,9 @@ bool rs_serve::launch() {
   }
   slot->reqs = std::move(batch);
   slot->busy = true;
+  slot->seq = ++launch_seq;
   std::lock_guard<std::mutex> lock(mu);
+  stats.launch_host_us += us_between(now, Clock::now());
   ++inflight;
   ++stats.batches;
   stats.peak_inflight_batches = std::max(stats.peak_inflight_batches, inflight);
@@ -312,20 +339,39 @@ bool rs_serve::launch() {
 void rs_serve::run() {
   (void)hipSetDevice(device);
   for (;;) {
+    const Clock::time_point t0 = Clock::now();
     bool progress = reap();
     admit();
+    const Clock::time_point t1 = Clock::now();
     while (launch()) progress = true;
+    bool all_busy = true;
+    Slot *oldest = nullptr;
+    for (Slot &sl : slots) {
+      if (!sl.busy) all_busy = false;
+      else if (!oldest || sl.seq < oldest->seq) oldest = &sl;
+    }
+    bool work_waiting;
     {
       std::unique_lock<std::mutex> lock(mu);
+      stats.admit_host_us += us_between(t0, t1);
       const bool idle = pending.empty() && admitted.empty() && inflight == 0;
       if (stopping && idle) break;
-      if (!progress) {
-        // Sleep until a submission arrives, or briefly while batches run.
-        if (idle)
-          cv_work.wait_for(lock, std::chrono::milliseconds(5));
-        else if (inflight > 0)
-          cv_work.wait_for(lock, std::chrono::microseconds(20));
+      work_waiting = !pending.empty() || !admitted.empty();
+      if (!progress && !oldest) {
+        // Nothing in flight: sleep until a submission arrives.
+        cv_work.wait_for(lock, std::chrono::milliseconds(5));
+        continue;
       }
+    }
+    if (!progress && oldest && (all_busy || work_waiting)) {
+      // Every slot is busy, or admission waits for budget: nothing can
+      // happen before the oldest batch finishes, so block on it.
+      (void)hipEventSynchronize(oldest->done);
+    } else if (!progress && oldest) {
+      // Slots free, nothing queued: wake on a submission or poll the
+      // running batches soon.
+      std::unique_lock<std::mutex> lock(mu);
+      cv_work.wait_for(lock, std::chrono::microseconds(50));
     }
   }
 }
@@ -333,6 +379,7 @@ void rs_serve::run() {
 rs_serve::~rs_serve() {
   for (Slot &s : slots) {
     if (s.batch) rs_poly_batch_free(s.batch);
+    if (s.start) (void)hipEventDestroy(s.start);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
   }
@@ -361,10 +408,12 @@ int rs_serve_create(const rs_serve_config_t *cfg, rs_serve_t **out) {
   for (Slot &sl : s->slots) {
     if (rc != RS_OK) break;
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+        hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.done) != hipSuccess)
       rc = RS_EDEVICE;
     else
       rc = rs_poly_batch_create(&sl.batch);
+    if (rc == RS_OK && cfg->max_block_bytes)
+      rc = rs_poly_batch_reserve(sl.batch, cfg->max_batch, cfg->max_block_bytes);
   }
   if (rc != RS_OK) {
     delete s;
@@ -409,10 +458,13 @@ int rs_serve_replay(rs_serve_t *s, const rs_serve_request_t *reqs, const double 
     for (size_t i = 0; i < moved->size(); ++i) {
       const auto at = t0 + std::chrono::duration_cast<Clock::duration>(
                                std::chrono::duration<double, std::micro>(times[i]));
-      while (Clock::now() < at) {
-        const auto left = at - Clock::now();
-        if (left > std::chrono::microseconds(200))
-          std::this_thread::sleep_for(left - std::chrono::microseconds(100));
+      // Sleep through long gaps; yield (rather than spin) through short
+      // ones so the scheduler and runtime threads keep their cores.
+      for (Clock::time_point now = Clock::now(); now < at; now = Clock::now()) {
+        if (at - now > std::chrono::microseconds(150))
+          std::this_thread::sleep_for(at - now - std::chrono::microseconds(100));
+        else
+          std::this_thread::yield();
       }
       Request *q = (*moved)[i].release();
       q->submitted = Clock::now();

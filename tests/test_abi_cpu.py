@@ -174,8 +174,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rs_poly_stripe_t), sizeof(rs_poly_launch_t),
          sizeof(rs_serve_config_t), sizeof(rs_serve_request_t),
          sizeof(rs_serve_completion_t), sizeof(rs_serve_stats_t));
-  printf("%zu %zu %zu\\n", offsetof(rs_serve_completion_t, out),
-         offsetof(rs_serve_completion_t, charge_bytes), offsetof(rs_serve_request_t, user_tag));
+  printf("%zu %zu %zu %zu\\n", offsetof(rs_serve_completion_t, out),
+         offsetof(rs_serve_completion_t, charge_bytes), offsetof(rs_serve_request_t, user_tag),
+         offsetof(rs_serve_config_t, max_block_bytes));
   return 0;
 }
 """)
@@ -190,4 +191,4 @@ int main(void) {
     assert got == want
     offs = [int(x) for x in lines[1].split()]
     assert offs == [B.ServeCompletion.out.offset, B.ServeCompletion.charge_bytes.offset,
-                    B.ServeRequest.user_tag.offset]
+                    B.ServeRequest.user_tag.offset, B.ServeConfig.max_block_bytes.offset]
