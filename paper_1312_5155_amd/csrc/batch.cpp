@@ -64,7 +64,7 @@ rs_poly_launch_t default_launch(int op, int wide) {
   } else {
     c.bytes_per_lane = 16;
     c.threads = wide ? 256 : 512;
-    c.tile_bytes = 64 << 10;
+    c.tile_bytes = wide ? 64 << 10 : 16 << 10;
   }
   c.wgs_per_cu = 2;
   return c;

@@ -113,7 +113,51 @@ struct Layout {
   static constexpr uint32_t kApplyReps = 128 / (M * kEntry);      // decode only
   static constexpr uint32_t kTableBytes = kApplyReps * kEntry;    // one apply table
   static constexpr uint32_t kApplyBase = 128;
+  // Lane groups at different rotation phases (m <= 4 only): in one LDS read
+  // group g uses copy (q + g) mod 4, so the copies' replicas together cover
+  // all 32 banks.
+  static constexpr uint32_t kPhases = M == 4 ? 32 / kLfsrReps : 1;
 };
+
+// Per-lane LDS addressing, computed once per kernel.  A lane of phase g keeps
+// its state rotated by g more bytes than the step count says: at unrolled
+// step q it reads feedback byte (q + g) mod 4 from copy (q + g) mod 4.  Data
+// enter rotated by g bytes and the state leaves un-rotated.  Decode lanes
+// likewise walk the apply tables in rotated order.
+template <int M, int MODE>
+struct Lanes {
+  uint32_t lsel[4], loff[4];   // LFSR step q: v_perm selector, byte offset
+  uint32_t rot_in, rot_out;    // v_alignbit shifts into / out of the phase
+  uint32_t asel[M], aoff[M];   // decode apply, slot b
+};
+
+template <int M, int MODE>
+__device__ __forceinline__ Lanes<M, MODE> make_lanes() {
+  using L = Layout<M, MODE>;
+  Lanes<M, MODE> t;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t g = (lane / L::kLfsrReps) % L::kPhases;
+  const uint32_t rep = lane & (L::kLfsrReps - 1);
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t p = (q + g) & 3;
+    t.lsel[q] = 0x0C0C0400u | (p << 8);
+    t.loff[q] = p * L::kCopyBytes + rep * L::kEntry;
+  }
+  t.rot_in = (32 - 8 * g) & 31;
+  t.rot_out = 8 * g;
+  if constexpr (MODE == kDecode) {
+    const uint32_t arep = lane & (L::kApplyReps - 1);
+    const uint32_t ga = M == 4 ? (lane / L::kApplyReps) % 4 : 0;
+#pragma unroll
+    for (uint32_t b = 0; b < (uint32_t)M; ++b) {
+      const uint32_t tb = M == 4 ? (b + ga) & 3 : b;
+      t.asel[b] = 0x0C0C0400u | ((tb & 3) << 8);
+      t.aoff[b] = L::kApplyBase + tb * L::kTableBytes + arep * L::kEntry;
+    }
+  }
+  return t;
+}
 
 // Expands the LFSR tables: copy v (0..3) of entry f is rotl(T'[f], 8(v+1)).
 template <int M, int MODE>
@@ -174,7 +218,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Loads W dwords (4*W byte columns starting at col) of one block.  The
 // vector form needs the whole chunk inside the block; the byte form reads
-// columns past the end of the block as zero.
+// columns past the end of the block as zero.  Every block byte is read (and
+// every output byte written) exactly once, so vector accesses carry the
+// non-temporal hint.
 template <int W, bool BYTEWISE>
 __device__ __forceinline__ void load_cols(const uint8_t *ptr, uint32_t col, uint32_t B,
                                           uint32_t (&a)[W]) {
@@ -182,13 +228,13 @@ __device__ __forceinline__ void load_cols(const uint8_t *ptr, uint32_t col, uint
   if (!BYTEWISE) {
     const global_ptr<const uint8_t> q = g + col;
     if constexpr (W == 4) {
-      const u32x4 v = *(const global_ptr<const u32x4>)q;
+      const u32x4 v = __builtin_nontemporal_load((const global_ptr<const u32x4>)q);
       a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
     } else if constexpr (W == 2) {
-      const u32x2 v = *(const global_ptr<const u32x2>)q;
+      const u32x2 v = __builtin_nontemporal_load((const global_ptr<const u32x2>)q);
       a[0] = v.x; a[1] = v.y;
     } else {
-      a[0] = *(const global_ptr<const uint32_t>)q;
+      a[0] = __builtin_nontemporal_load((const global_ptr<const uint32_t>)q);
     }
   } else {
 #pragma unroll
@@ -211,11 +257,11 @@ __device__ __forceinline__ void store_cols(uint8_t *ptr, uint32_t col, uint32_t 
   if (!BYTEWISE) {
     const global_ptr<uint8_t> q = g + col;
     if constexpr (W == 4) {
-      *(global_ptr<u32x4>)q = u32x4{a[0], a[1], a[2], a[3]};
+      __builtin_nontemporal_store(u32x4{a[0], a[1], a[2], a[3]}, (global_ptr<u32x4>)q);
     } else if constexpr (W == 2) {
-      *(global_ptr<u32x2>)q = u32x2{a[0], a[1]};
+      __builtin_nontemporal_store(u32x2{a[0], a[1]}, (global_ptr<u32x2>)q);
     } else {
-      *(global_ptr<uint32_t>)q = a[0];
+      __builtin_nontemporal_store(a[0], (global_ptr<uint32_t>)q);
     }
   } else {
 #pragma unroll
@@ -229,20 +275,18 @@ __device__ __forceinline__ void store_cols(uint8_t *ptr, uint32_t col, uint32_t 
   }
 }
 
-// One LFSR step at window position q (compile time) for one column.
+// One LFSR step at unrolled window position q for one column.
 template <int M, int MODE>
 __device__ __forceinline__ void lfsr_step(uint32_t (&s)[M / 4], const uint8_t *lds,
-                                          uint32_t loff, int q) {
-  using L = Layout<M, MODE>;
+                                          const Lanes<M, MODE> &t, int q) {
   const int bp = q & 3;
-  const uint32_t sel = 0x0C0C0400u | ((uint32_t)bp << 8);
   if constexpr (M == 4) {
-    const uint32_t addr = perm(s[0], loff, sel);
-    s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr + bp * L::kCopyBytes);
+    const uint32_t addr = perm(s[0], t.loff[bp], t.lsel[bp]);
+    s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
   } else {
     const int half = q >> 2;
-    const uint32_t addr = perm(s[half], loff, sel);
-    const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr + bp * L::kCopyBytes);
+    const uint32_t addr = perm(s[half], t.loff[bp], t.lsel[bp]);
+    const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
     if (half == 0) {
       s[0] ^= v.x;
       s[1] ^= v.y;
@@ -350,28 +394,41 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
 }
 
 // XORs an item into the column states (transposed so that each column's M
-// symbols fill its state window), then, for an LFSR group, runs its M steps.
+// symbols fill its state window; for an LFSR group rotated into the lane's
+// phase), then, for an LFSR group, runs its M steps.
 template <int M, int W, int MODE>
 __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
-                                            bool lfsr, const uint8_t *lds, uint32_t loff) {
+                                            bool lfsr, const uint8_t *lds,
+                                            const Lanes<M, MODE> &t) {
   constexpr int NQ = M / 4;
   constexpr int NC = 4 * W;
 #pragma unroll
   for (int w = 0; w < W; ++w)
 #pragma unroll
     for (int h = 0; h < NQ; ++h) {
-      uint32_t d0, d1, d2, d3;
-      transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d0, d1, d2, d3);
-      s[4 * w + 0][h] ^= d0;
-      s[4 * w + 1][h] ^= d1;
-      s[4 * w + 2][h] ^= d2;
-      s[4 * w + 3][h] ^= d3;
+      uint32_t d[4];
+      transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[0], d[1],
+                 d[2], d[3]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        if (M == 4 && lfsr) d[x] = __builtin_amdgcn_alignbit(d[x], d[x], t.rot_in);
+        s[4 * w + x][h] ^= d[x];
+      }
     }
   if (lfsr) {
 #pragma unroll
     for (int q = 0; q < M; ++q)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) lfsr_step<M, MODE>(s[c], lds, loff, q);
+      for (int c = 0; c < NC; ++c) lfsr_step<M, MODE>(s[c], lds, t, q);
+  }
+}
+
+// Brings the column states back from the lane's rotation phase.
+template <int M, int W, int MODE>
+__device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lanes<M, MODE> &t) {
+  if constexpr (M == 4) {
+#pragma unroll
+    for (int c = 0; c < 4 * W; ++c) s[c][0] = __builtin_amdgcn_alignbit(s[c][0], s[c][0], t.rot_out);
   }
 }
 
@@ -383,7 +440,7 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
 template <int M, int W, int MODE, bool BYTEWISE, class Src>
 __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool active,
                                              uint32_t (&s)[4 * W][M / 4], const uint8_t *lds,
-                                             uint32_t aoff) {
+                                             const Lanes<M, MODE> &t) {
   constexpr int NQ = M / 4;
   constexpr int NC = 4 * W;
   const int m = src.m(), n_out = src.n_out();
@@ -395,17 +452,16 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
       for (int h = 0; h < NQ; ++h) L[c][h] = 0;
 #pragma unroll
     for (int b = 0; b < M; ++b) {
-      if (b < m) {
-        constexpr uint32_t base = Layout<M, kDecode>::kApplyBase;
-        const uint32_t tab = base + b * Layout<M, kDecode>::kTableBytes;
-        const uint32_t sel = 0x0C0C0400u | ((uint32_t)(b & 3) << 8);
+      // m <= 4: every lane walks all 4 tables (those past m are zero) in its
+      // rotated order; m > 4: tables b < m in order.
+      if (M == 4 || b < m) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const uint32_t addr = perm(s[c][b >> 2], aoff, sel);
+          const uint32_t addr = perm(s[c][M == 4 ? 0 : b >> 2], t.aoff[b], t.asel[b]);
           if constexpr (M == 4) {
-            L[c][0] ^= *reinterpret_cast<const uint32_t *>(lds + addr + tab);
+            L[c][0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
           } else {
-            const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr + tab);
+            const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
             L[c][0] ^= v.x;
             L[c][1] ^= v.y;
           }
@@ -445,8 +501,7 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
 template <int M, int W, int MODE, bool BYTEWISE, class Src>
 __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uint32_t n,
                                                 uint32_t lane, uint32_t lanes,
-                                                const uint8_t *lds, uint32_t loff,
-                                                uint32_t aoff) {
+                                                const uint8_t *lds, const Lanes<M, MODE> &t) {
   constexpr uint32_t NC = 4 * W;
   if (n == 0) return;
   const int groups = src.k_pad() / M;
@@ -479,9 +534,10 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
     const bool more = nr < rounds;
     // past the last item the prefetch repeats the current one (and is unused)
     load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, nxt);
-    absorb_item<M, W, MODE>(s, cur, g < groups, lds, loff);
+    absorb_item<M, W, MODE>(s, cur, g < groups, lds, t);
+    if (g == groups - 1) unrotate<M, W, MODE>(s, t);
     if (g == items - 1) {
-      finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, aoff);
+      finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, t);
 #pragma unroll
       for (int c = 0; c < 4 * W; ++c)
 #pragma unroll
@@ -503,25 +559,13 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
 template <int M, int W, int MODE, class Src>
 __device__ __forceinline__ void process_range(const Src &src, uint32_t c0, uint32_t c1,
                                               uint32_t lane, uint32_t lanes, const uint8_t *lds,
-                                              uint32_t loff, uint32_t aoff) {
+                                              const Lanes<M, MODE> &t) {
   constexpr uint32_t NC = 4 * W;
   const uint32_t n_full = (c1 - c0) / NC;
-  process_columns<M, W, MODE, false>(src, c0, n_full, lane, lanes, lds, loff, aoff);
+  process_columns<M, W, MODE, false>(src, c0, n_full, lane, lanes, lds, t);
   const uint32_t tail = c0 + n_full * NC;
   if (tail < c1 && lane == 0)
-    process_columns<M, 1, MODE, true>(src, tail, (c1 - tail + 3) / 4, 0, 1, lds, loff, aoff);
-}
-
-template <int M, int MODE>
-__device__ __forceinline__ uint32_t lfsr_lane_offset() {
-  using L = Layout<M, MODE>;
-  return (threadIdx.x & (L::kLfsrReps - 1)) * L::kEntry;
-}
-
-template <int M>
-__device__ __forceinline__ uint32_t apply_lane_offset() {
-  using L = Layout<M, kDecode>;
-  return (threadIdx.x & (L::kApplyReps - 1)) * L::kEntry;
+    process_columns<M, 1, MODE, true>(src, tail, (c1 - tail + 3) / 4, 0, 1, lds, t);
 }
 
 constexpr uint32_t kLdsBytes = 256 * kRowBytes;
@@ -544,14 +588,14 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) codec_kernel(CodecParams p)
 
   constexpr uint32_t NC = 4 * W;
   const PlainSrc src{p};
-  const uint32_t loff = lfsr_lane_offset<M, MODE>(), aoff = apply_lane_offset<M>();
+  const Lanes<M, MODE> t = make_lanes<M, MODE>();
   const uint32_t lane = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lanes = gridDim.x * blockDim.x;
   const uint32_t B = (uint32_t)p.block_bytes;
   if constexpr (BYTEWISE)
-    process_columns<M, W, MODE, true>(src, 0, (B + NC - 1) / NC, lane, lanes, lds, loff, aoff);
+    process_columns<M, W, MODE, true>(src, 0, (B + NC - 1) / NC, lane, lanes, lds, t);
   else
-    process_range<M, W, MODE>(src, 0, B, lane, lanes, lds, loff, aoff);
+    process_range<M, W, MODE>(src, 0, B, lane, lanes, lds, t);
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) {
@@ -600,7 +644,7 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
   const_as<uint32_t> tile_stripe = as_const(g.tile_stripe);
   unsigned long long *counter = reinterpret_cast<unsigned long long *>(&hdr->counter);
   const uint32_t tile_cols = chdr->tile_cols;
-  const uint32_t loff = lfsr_lane_offset<M, MODE>(), aoff = apply_lane_offset<M>();
+  const Lanes<M, MODE> lt = make_lanes<M, MODE>();
   uint32_t staged_lfsr = ~0u, staged_apply = ~0u;
 
   if (threadIdx.x == 0) next_tile = atomicAdd(counter, 1ull);
@@ -630,7 +674,7 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
     const TableSrc src{ptr_table + d.ptr_off, bytes, d.k, d.m, d.k_pad, d.n_out, g.zero_page};
     const uint32_t c0 = (uint32_t)(tile - d.tile_begin) * tile_cols;
     const uint32_t c1 = bytes - c0 > tile_cols ? c0 + tile_cols : bytes;
-    process_range<M, W, MODE>(src, c0, c1, threadIdx.x, blockDim.x, lds, loff, aoff);
+    process_range<M, W, MODE>(src, c0, c1, threadIdx.x, blockDim.x, lds, lt);
     __syncthreads();   // tables and next_tile are about to change
   }
 }
