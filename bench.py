@@ -54,6 +54,8 @@ def measured_traffic(kernel, src_hash):
 
 
 CALIB_BYTES = 1 << 30       # size of the copy that calibrates the counters
+# bench.py arguments of the counter runs (timed steps only, no serving)
+PMC_BENCH_ARGS = "--steps 3 --warmup 1 --plain-steps 0 --cpu-sample 0 --serving-requests 0"
 
 
 def calibrate_copy():
@@ -108,7 +110,10 @@ def traffic_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path
                        ("batch_encode", "batch_kernel<4, 1, 0>"),
                        ("batch_decode", "batch_kernel<4, 4, 1>"),
                        ("batch_decode", "batch_kernel<4, 2, 1>"),
-                       ("batch_decode", "batch_kernel<4, 1, 1>")):
+                       ("batch_decode", "batch_kernel<4, 1, 1>"),
+                       ("batch_update", "batch_kernel<4, 4, 2>"),
+                       ("batch_update", "batch_kernel<4, 2, 2>"),
+                       ("batch_update", "batch_kernel<4, 1, 2>")):
         fv = [v for n, (v, c) in fetch.items() if key in n]
         wv = [v for n, (v, c) in write.items() if key in n]
         if not fv or not wv:
@@ -120,7 +125,7 @@ def traffic_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path
     cmd = "rocprofv3 --pmc {c} -d <out> -o run --output-format csv -- python3 bench.py {a}"
     rec = {"workload": "rs104_256x1MiB", "kernel_source_hash": kernel_source_hash(),
            "commands": [cmd.format(c=c, a=a) for c in ("FETCH_SIZE", "WRITE_SIZE") for a in (
-               "--steps 3 --warmup 1 --plain-steps 0 --cpu-sample 0", "--calibrate-copy")] +
+               PMC_BENCH_ARGS, "--calibrate-copy")] +
            ["python3 bench.py --traffic-from <FETCH csv> <WRITE csv> <calibration FETCH csv> "
             "<calibration WRITE csv>"],
            "note": "counter values are KiB per dispatch; each is scaled by what it reads for "
@@ -213,7 +218,8 @@ def serving(fractions, count):
 
 def cpu_baseline(host_stripes, erasures, threads):
     """The oracle, unchanged, on a bounded sample: encode then decode of each
-    sampled stripe; stripes run in parallel threads (ctypes drops the GIL)."""
+    sampled stripe; stripes run in parallel threads (ctypes drops the GIL).
+    Returns (GB/s of user data, seconds, the oracle's parity per stripe)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -227,14 +233,124 @@ def cpu_baseline(host_stripes, erasures, threads):
         full = np.concatenate([data, par])
         full[erasures[i]] = 0
         oracle.decode(F, K, M, full, erasures[i])
-        return full
+        return par
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, range(len(host_stripes))))
+        parity = list(ex.map(one, range(len(host_stripes))))
     dt = time.perf_counter() - t0
     user = 2 * len(host_stripes) * K * BLOCK
-    return user / dt / 1e9, dt
+    return user / dt / 1e9, dt, parity
+
+
+def build_workload(name, dev):
+    """Device arena, per-stripe (k, m, B, block pointers) and decode erasure
+    lists of a parity workload: the mixed uneven batch or RS(32,8)."""
+    import torch
+
+    import workloads
+    cfg = workloads.CONFIGS[name]
+    rng = workloads.meta_rng(workloads.meta_seed(cfg["index"]))
+    if name == "mixed_4096_uneven":
+        sizes = workloads.log_uniform_sizes(rng, cfg["stripes"], cfg["min_bytes"],
+                                            cfg["max_bytes"])
+        picks = rng.integers(0, len(cfg["codes"]), size=cfg["stripes"])
+        shapes = [(*cfg["codes"][c], int(b)) for c, b in zip(picks, sizes)]
+    else:
+        shapes = [(cfg["k"], cfg["m"], cfg["block_bytes"])] * cfg["stripes"]
+    offsets, off = [], 0
+    for (k, m, nb) in shapes:
+        step = (nb + 255) // 256 * 256
+        offsets.append([off + b * step for b in range(k + m)])
+        off += (k + m) * step
+    buf = torch.empty(off, dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(workloads.data_seed(cfg["index"]))
+    chunk = 1 << 30
+    for c0 in range(0, off, chunk):
+        n = min(chunk, off - c0)
+        buf[c0:c0 + n] = torch.randint(0, 256, (n,), dtype=torch.uint8, device=dev,
+                                       generator=gen)
+    base = buf.data_ptr()
+    stripes, erasures = [], []
+    for (k, m, nb), offs in zip(shapes, offsets):
+        stripes.append((k, m, nb, [base + o for o in offs]))
+        t = m if name == "rs328_64x16MiB" else int(rng.integers(1, m + 1))
+        erasures.append(workloads.random_erasures(rng, k + m, t))
+    return buf, stripes, erasures
+
+
+def other_workload(name, args):
+    """Batched (and plain) encode + decode of another workload; one JSON line
+    with each kernel's time, algorithmic HBM bytes and fraction of peak."""
+    import torch
+
+    from paper_1312_5155_amd import binding as B
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    buf, stripes, erasures = build_workload(name, dev)
+    codes = {}
+    for (k, m, _, _) in stripes:
+        codes.setdefault((k, m), B.Code(k, m))
+    enc = B.StripeArray([(codes[(k, m)], p, nb) for (k, m, nb, p) in stripes])
+    dec = B.StripeArray([(codes[(k, m)], p, nb, e, 0)
+                         for (k, m, nb, p), e in zip(stripes, erasures)])
+    batch = B.Batch()
+    if args.tune:
+        batch.tune(B.RS_POLY_OP_ENCODE, enc, stream)
+        batch.tune(B.RS_POLY_OP_DECODE, dec, stream)
+    for _ in range(args.warmup):
+        batch.encode(enc, stream)
+        batch.decode(dec, stream)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        batch.encode(enc, stream)
+        ev[i][1].record(stream)
+        batch.decode(dec, stream)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    enc_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    dec_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    user = sum(k * nb for (k, m, nb, _) in stripes)
+    enc_alg = sum((k + m) * nb for (k, m, nb, _) in stripes)
+    dec_alg = sum((k + len(e)) * nb for (k, m, nb, _), e in zip(stripes, erasures))
+
+    plain = None
+    if args.plain_steps > 0:
+        def plain_step():
+            for (k, m, nb, p) in stripes:
+                B.rs_poly_encode(codes[(k, m)].handle, p[:k], p[k:], nb, stream)
+            for (k, m, nb, p), e in zip(stripes, erasures):
+                B.rs_poly_decode(codes[(k, m)].handle, p, nb, e, 0, stream)
+        plain_step()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+        plain = {"ms_per_step": round(plain_ms, 3),
+                 "value": round(2 * user / (plain_ms / 1e3) / 1e9, 1),
+                 "launches_per_step": 2 * len(stripes)}
+
+    def kern(ms, alg):
+        gbs = alg / (ms / 1e3) / 1e9
+        return {"avg_ms": round(ms, 4), "alg_bytes": alg, "gbs": round(gbs, 1),
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "user_gbs": round(user / (ms / 1e3) / 1e9, 1)}
+
+    out = {"workload": name, "stripes": len(stripes), "user_bytes": user,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "value": round(2 * user / (ms_per_step / 1e3) / 1e9, 1), "unit": "GB/s",
+           "kernels": {"batch_encode": kern(enc_ms, enc_alg), "batch_decode": kern(dec_ms, dec_alg)},
+           "launch": {"encode": [batch.get_launch(B.RS_POLY_OP_ENCODE, w).as_dict() for w in (0, 1)],
+                      "decode": [batch.get_launch(B.RS_POLY_OP_DECODE, w).as_dict() for w in (0, 1)]},
+           "plain": plain}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -245,6 +361,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=48,
                     help="stripes the CPU oracle encodes+decodes (0 = skip)")
+    ap.add_argument("--update-steps", type=int, default=10,
+                    help="timed batched delta-parity updates (one changed block per "
+                         "stripe; rounded up to even so the parity ends unchanged)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this workload before timing")
     ap.add_argument("--serving-requests", type=int, default=10000,
@@ -256,6 +375,10 @@ def main():
     ap.add_argument("--traffic-from", nargs=4, metavar="CSV",
                     help="FETCH, WRITE, calibration FETCH, calibration WRITE "
                          "counter_collection.csv files -> profiles/ traffic JSON")
+    ap.add_argument("--workload", default="rs104_256x1MiB",
+                    choices=["rs104_256x1MiB", "mixed_4096_uneven", "rs328_64x16MiB"],
+                    help="the headline workload, or another one measured on its own "
+                         "(encode + decode kernels, no CPU or serving legs)")
     args = ap.parse_args()
 
     if args.traffic_from:
@@ -276,6 +399,9 @@ def main():
               "(stripes shard across GPUs with no exchange); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload != "rs104_256x1MiB":
+        other_workload(args.workload, args)
+        return
 
     import torch
 
@@ -356,13 +482,46 @@ def main():
                  "value": round(2 * user_per_op / (plain_ms / 1e3) / 1e9, 1),
                  "launches_per_step": 2 * STRIPES}
 
-    # The output must still be a valid codeword set: spot-check stripe 0.
-    import numpy as np
+    # Delta-parity update (Sec. 3.2 update property), a small write: one
+    # changed data block per stripe; reads the delta and the parity, writes
+    # the parity.  An even number of runs leaves the parity as it was.
+    update = None
+    n_upd = args.update_steps + (args.update_steps & 1)
+    if n_upd > 0:
+        delta = torch.randint(0, 256, (STRIPES, BLOCK), dtype=torch.uint8, device=dev,
+                              generator=gen)
+        changed = workloads.meta_rng(workloads.meta_seed(1) + 2).integers(0, K, size=STRIPES)
+        upd_ents = []
+        for s in range(STRIPES):
+            p = [None] * K + ptrs[s][K:]
+            p[int(changed[s])] = delta[s].data_ptr()
+            upd_ents.append((code, p, BLOCK))
+        upd = B.StripeArray(upd_ents)
+        batch.update(upd, stream)
+        batch.update(upd, stream)
+        u0 = torch.cuda.Event(enable_timing=True)
+        u1 = torch.cuda.Event(enable_timing=True)
+        u0.record(stream)
+        for _ in range(n_upd):
+            batch.update(upd, stream)
+        u1.record(stream)
+        torch.cuda.synchronize()
+        upd_ms = u0.elapsed_time(u1) / n_upd
+        upd_alg = STRIPES * (1 + 2 * M) * BLOCK
+        update = {"avg_ms": round(upd_ms, 4), "alg_bytes": upd_alg,
+                  "gbs": round(upd_alg / (upd_ms / 1e3) / 1e9, 1),
+                  "user_gbs": round(STRIPES * BLOCK / (upd_ms / 1e3) / 1e9, 1),
+                  "changed_blocks_per_stripe": 1}
+        del delta
 
-    import oracle
-    F = oracle.Field(8, 0x11D)
-    host0 = buf[0].cpu().numpy()
-    assert np.array_equal(oracle.encode(F, K, M, host0[:K]), host0[K:]), "parity check failed"
+    # Self-consistency of the timed buffers (GPU path only): wiping stripe
+    # 0's erased blocks and decoding again restores them.
+    before = buf[0].clone()
+    buf[0, erasures[0]] = 0
+    B.rs_poly_decode(code.handle, ptrs[0], BLOCK, erasures[0], 0, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[0], before), "decode did not restore stripe 0"
+    del before
 
     src_hash = kernel_source_hash()
     kernels = {
@@ -371,6 +530,10 @@ def main():
         "batch_decode": {"avg_ms": round(dec_ms, 4), "alg_bytes": dec_alg,
                          "gbs": round(dec_alg / (dec_ms / 1e3) / 1e9, 1)},
     }
+    if update:
+        kernels["batch_update"] = update
+    for label in kernels:
+        kernels[label]["traffic"] = measured_traffic(label, src_hash)
     dom = "batch_encode" if enc_ms >= dec_ms else "batch_decode"
     achieved = kernels[dom]["gbs"]
     traffic = measured_traffic(dom, src_hash)
@@ -383,10 +546,15 @@ def main():
         n = min(args.cpu_sample, STRIPES)
         host = [buf[s, :K].cpu().numpy() for s in range(n)]
         threads = min(16, os.cpu_count() or 1)
-        gbs, secs = cpu_baseline(host, erasures[:n], threads)
+        gbs, secs, want = cpu_baseline(host, erasures[:n], threads)
+        # the GPU's parity of the sampled stripes against the oracle's
+        exact = all((buf[s, K:].cpu().numpy() == want[s]).all() for s in range(n))
         cpu = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
                "sample": f"{n} of the {STRIPES} stripes, encode + decode each "
-                         f"({secs:.1f} s wall on {threads} threads)"}
+                         f"({secs:.1f} s wall on {threads} threads)",
+               "gpu_parity_matches_oracle": bool(exact)}
+        if not exact:
+            raise SystemExit("GPU parity differs from the oracle on the CPU sample")
 
     serve = None
     if args.serving_requests > 0:

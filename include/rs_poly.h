@@ -110,6 +110,24 @@ int rs_poly_generator(const rs_poly_t *h, uint8_t *g);
 int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data,
                    uint8_t *const *parity, size_t block_bytes, void *stream);
 
+/* Delta-parity update (the update property of Sec. 3.2): encoding is
+ * linear, so when data blocks change, the parity of the new data is the old
+ * parity plus the encoding of the data difference.  For every byte column c,
+ *     parity[i][c] ^= coefficient i of x^m * sum_j delta[j][c] x^j mod g(x),
+ * in one pass that reads the delta blocks and the parity and writes the
+ * parity in place.
+ *   delta    host array of k device pointers; delta[j] is the XOR of new and
+ *            old data block j (read only), or NULL for an unchanged block,
+ *            which is not read.  All NULL is a successful no-op.
+ *   parity   host array of m device pointers to the current parity blocks
+ *            (read and overwritten)
+ *   block_bytes  bytes per block; 0 is a successful no-op
+ * Applying the same delta twice restores the parity.  Parity buffers must
+ * not overlap delta buffers or each other.
+ * Errors: RS_ENULL (h, delta, parity, or a parity entry), RS_EDEVICE. */
+int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta,
+                   uint8_t *const *parity, size_t block_bytes, void *stream);
+
 /* Erasure decode (Sec. 3.3): rebuilds, in place, exactly the blocks named in
  * erasures[0..n_erasures), data or parity, from the surviving blocks.
  *   blocks      host array of n = k+m device pointers, API block order
@@ -156,7 +174,9 @@ typedef struct rs_poly_stripe {
     rs_poly_t *code;             /* its code handle                          */
     uint8_t *const *blocks;      /* host array of n = k+m device pointers,   *
                                   * API block order (encode: reads 0..k-1,   *
-                                  * writes k..n-1)                           */
+                                  * writes k..n-1; update: 0..k-1 are delta  *
+                                  * blocks or NULL, k..n-1 the parity,       *
+                                  * updated in place)                        */
     size_t block_bytes;          /* bytes per block; 0 = nothing to do       */
     const int *erasures;         /* decode only: lost API indices            */
     int n_erasures;              /* decode only: t, 0 <= t <= m              */
@@ -176,6 +196,7 @@ typedef struct rs_poly_launch {
 
 #define RS_POLY_OP_ENCODE 0
 #define RS_POLY_OP_DECODE 1
+#define RS_POLY_OP_UPDATE 2
 
 typedef struct rs_poly_batch rs_poly_batch_t;
 
@@ -206,6 +227,13 @@ int rs_poly_batch_encode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
 int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
                          int count, void *stream);
 
+/* Delta-parity updates (as rs_poly_update) of every stripe, with one graph
+ * launch per state width.  Every non-NULL block pointer must be 16-byte
+ * aligned; the parity of different stripes must not overlap.
+ * Errors: RS_ENULL, RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
+int rs_poly_batch_update(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
+                         int count, void *stream);
+
 /* Pre-sizes the object's device descriptor buffers, tile map and pinned
  * staging for calls of up to max_stripes stripes of up to max_block_bytes
  * each (any codes), so such calls never allocate.  Larger calls still work:
@@ -223,7 +251,9 @@ int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide,
                              const rs_poly_launch_t *cfg);
 
 /* Autotuner: times every candidate launch shape on these stripes (running
- * the real operation, which is idempotent, several times on `stream`),
+ * the real operation several times on `stream`: encode and decode are
+ * idempotent, and an update runs an even number of times per candidate, so
+ * the parity ends as it began -- tuning does not apply the update),
  * keeps the fastest for each state width present, and returns the shape
  * chosen for the width carrying the most bytes in *best (may be NULL).
  * Blocks until the timing runs finish.  If the environment variable

@@ -59,6 +59,7 @@ def load():
     lib.rs_poly_strerror.restype = ctypes.c_char_p
     lib.rs_poly_generator.argtypes = [vp, u8p]
     lib.rs_poly_encode.argtypes = [vp, pp, pp, sz, vp]
+    lib.rs_poly_update.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_decode.argtypes = [vp, pp, sz, ip, i, u, vp]
     lib.rs_poly_decode_plan.argtypes = [vp, ip, i, u, ip, ip, u8p]
     sp = ctypes.POINTER(Stripe)
@@ -68,6 +69,7 @@ def load():
     lib.rs_poly_batch_free.restype = None
     lib.rs_poly_batch_encode.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_decode.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_batch_update.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_reserve.argtypes = [vp, i, sz]
     lib.rs_poly_batch_get_launch.argtypes = [vp, i, i, lp]
     lib.rs_poly_batch_set_launch.argtypes = [vp, i, i, lp]
@@ -145,6 +147,7 @@ class Launch(ctypes.Structure):
 
 RS_POLY_OP_ENCODE = 0
 RS_POLY_OP_DECODE = 1
+RS_POLY_OP_UPDATE = 2
 
 
 def check(rc, where):
@@ -206,6 +209,12 @@ def rs_poly_encode(h, data, parity, block_bytes, stream=None):
                  "rs_poly_encode")
 
 
+def rs_poly_update(h, delta, parity, block_bytes, stream=None):
+    d, p = _ptr_array(delta), _ptr_array(parity)
+    return check(load().rs_poly_update(h, d, p, block_bytes, _stream(stream)),
+                 "rs_poly_update")
+
+
 def rs_poly_decode(h, blocks, block_bytes, erasures, flags=0, stream=None):
     b = _ptr_array(blocks)
     er = (ctypes.c_int * max(1, len(erasures)))(*erasures)
@@ -228,7 +237,8 @@ def rs_poly_decode_plan(h, n, m, erasures, flags=0):
 class StripeArray:
     """A prepared rs_poly_stripe_t array (and the host arrays it points to),
     reusable across batch calls.  Entries: (code, blocks, block_bytes) for
-    encode, plus (erasures, flags) for decode."""
+    encode and update (update: blocks 0..k-1 are delta blocks or None), plus
+    (erasures, flags) for decode."""
 
     def __init__(self, entries):
         self.count = len(entries)
@@ -271,6 +281,12 @@ def rs_poly_batch_decode(b, stripes, stream=None):
     sa = _stripes(stripes)
     return check(load().rs_poly_batch_decode(b, sa.arr, sa.count, _stream(stream)),
                  "rs_poly_batch_decode")
+
+
+def rs_poly_batch_update(b, stripes, stream=None):
+    sa = _stripes(stripes)
+    return check(load().rs_poly_batch_update(b, sa.arr, sa.count, _stream(stream)),
+                 "rs_poly_batch_update")
 
 
 def rs_poly_batch_get_launch(b, op, wide):
@@ -328,6 +344,13 @@ class Code:
             block_bytes = data[0].numel()
         return rs_poly_encode(self._h, list(data), list(parity), block_bytes, stream)
 
+    def update(self, delta, parity, block_bytes=None, stream=None):
+        """parity ^= encode(delta) in place; None entries of delta are
+        unchanged blocks."""
+        if block_bytes is None:
+            block_bytes = parity[0].numel()
+        return rs_poly_update(self._h, list(delta), list(parity), block_bytes, stream)
+
     def decode(self, blocks, erasures, block_bytes=None, flags=0, stream=None):
         if block_bytes is None:
             block_bytes = next(b for b in blocks if b is not None).numel()
@@ -363,6 +386,9 @@ class Batch:
 
     def decode(self, stripes, stream=None):
         return rs_poly_batch_decode(self._b, stripes, stream)
+
+    def update(self, stripes, stream=None):
+        return rs_poly_batch_update(self._b, stripes, stream)
 
     def reserve(self, max_stripes, max_block_bytes):
         return check(load().rs_poly_batch_reserve(self._b, max_stripes, max_block_bytes),

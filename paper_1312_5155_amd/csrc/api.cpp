@@ -109,6 +109,28 @@ void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *cons
   memcpy(p->lfsr_basis, c.lfsr_basis(), sizeof(p->lfsr_basis));
 }
 
+int update_span(const Code &c, const uint8_t *const *delta) {
+  int span = 0;
+  for (int j = 0; j < c.k(); ++j)
+    if (delta[j]) span = j + 1;
+  return span;
+}
+
+void fill_update_params(const Code &c, const uint8_t *const *delta, uint8_t *const *parity,
+                        int span, uint64_t offset, uint64_t B, CodecParams *p) {
+  for (int j = 0; j < span; ++j) p->data[j] = delta[j] ? delta[j] + offset : nullptr;
+  for (int i = 0; i < c.m(); ++i) {
+    p->par_in[i] = parity[i] + offset;
+    p->out[i] = parity[i] + offset;
+  }
+  p->block_bytes = B;
+  p->k = span;
+  p->m = c.m();
+  p->k_pad = round_up(span, c.state_bytes());
+  p->n_out = c.m();
+  memcpy(p->lfsr_basis, c.lfsr_basis(), sizeof(p->lfsr_basis));
+}
+
 void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
                         const int *sorted, int t, uint64_t offset, uint64_t B,
                         CodecParams *p) {
@@ -198,6 +220,40 @@ int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data, uint8_t *const *par
     p.zero_page = zp;
     const LaunchCfg cfg = default_cfg(kEncode, c.state_bytes(), piece, align, ncu);
     const int rc = hip_status(launch_codec(kEncode, c.state_bytes(), p, cfg, stream));
+    if (rc != RS_OK) return rc;
+  }
+  return RS_OK;
+}
+
+int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta, uint8_t *const *parity,
+                   size_t block_bytes, void *stream) {
+  if (!h || !delta || !parity) return RS_ENULL;
+  const Code &c = h->code;
+  int align = 16;
+  for (int j = 0; j < c.k(); ++j)
+    if (delta[j]) align = std::min(align, pointer_alignment(delta[j]));
+  for (int i = 0; i < c.m(); ++i) {
+    if (!parity[i]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(parity[i]));
+  }
+  // Blocks above the highest changed one contribute nothing: the LFSR
+  // starts there.  No changed block at all leaves the parity as it is.
+  const int span = update_span(c, delta);
+  if (block_bytes == 0 || span == 0) return RS_OK;
+
+  std::lock_guard<std::mutex> lock(h->mu);
+  const int ncu = device_cu_count();
+  const uint8_t *zp = device_zero_page();
+  if (ncu <= 0 || !zp) return RS_EDEVICE;
+  const int sb = c.state_bytes();
+  for (uint64_t off = 0; off < block_bytes; off += kMaxPieceBytes) {
+    const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
+    CodecParams p;
+    memset(&p, 0, sizeof(p));
+    fill_update_params(c, delta, parity, span, off, piece, &p);
+    p.zero_page = zp;
+    const LaunchCfg cfg = default_cfg(kUpdate, sb, piece, align, ncu);
+    const int rc = hip_status(launch_codec(kUpdate, sb, p, cfg, stream));
     if (rc != RS_OK) return rc;
   }
   return RS_OK;

@@ -1,4 +1,4 @@
-// Batched encode/decode: stripe descriptors, pinned staging, graph capture
+// Batched encode/decode/update: stripe descriptors, pinned staging, graph capture
 // and replay, and the launch-shape autotuner with its cache file.
 #include <hip/hip_runtime_api.h>
 #include <stdio.h>
@@ -23,7 +23,7 @@
 namespace rsp {
 namespace {
 
-constexpr int kOps = 2;     // encode, decode
+constexpr int kOps = 3;     // encode, decode, update
 constexpr int kWidths = 2;  // state width 4 bytes (m <= 4), 8 bytes (m <= 8)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -57,7 +57,7 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
 // MI355X (the autotuner refines them per workload).
 rs_poly_launch_t default_launch(int op, int wide) {
   rs_poly_launch_t c;
-  if (op == RS_POLY_OP_ENCODE && !wide) {
+  if (op != RS_POLY_OP_DECODE && !wide) {
     c.bytes_per_lane = 8;
     c.threads = 1024;
     c.tile_bytes = 16 << 10;
@@ -207,8 +207,10 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
   GraphEntry e;
   if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return RS_EDEVICE;
-  const int lerr = launch_batch(op == RS_POLY_OP_DECODE ? kDecode : kEncode, wide ? 8 : 4, g,
-                                gb.tile_cap, lc, capture);
+  const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
+                    : op == RS_POLY_OP_UPDATE ? kUpdate
+                                              : kEncode;
+  const int lerr = launch_batch(mode, wide ? 8 : 4, g, gb.tile_cap, lc, capture);
   const hipError_t cerr = hipStreamEndCapture(capture, &e.graph);
   if (lerr != 0 || cerr != hipSuccess) {
     if (e.graph) (void)hipGraphDestroy(e.graph);
@@ -266,6 +268,14 @@ int check_stripe(int op, const rs_poly_stripe_t &st, int *sorted,
     }
     return RS_OK;
   }
+  if (op == RS_POLY_OP_UPDATE) {
+    // delta blocks may be NULL (unchanged); parity blocks are required
+    for (int b = 0; b < k + m; ++b) {
+      if (!st.blocks[b] && b >= k) return RS_ENULL;
+      if (st.blocks[b] && !aligned(st.blocks[b])) return RS_EINVAL;
+    }
+    return RS_OK;
+  }
   const int rc = validate_erasures(c, st.erasures, st.n_erasures, st.flags, sorted);
   if (rc != RS_OK) return rc;
   if (st.n_erasures == 0) return RS_OK;
@@ -296,8 +306,10 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     std::shared_ptr<const DecodePlan> dp;
     const int rc = check_stripe(op, st, sorted, &dp);
     if (rc != RS_OK) return rc;
-    if (st.block_bytes == 0 || (op == RS_POLY_OP_DECODE && st.n_erasures == 0)) continue;
     const Code &c = st.code->code;
+    const int span = op == RS_POLY_OP_UPDATE ? update_span(c, st.blocks) : c.k();
+    if (st.block_bytes == 0 || (op == RS_POLY_OP_DECODE && st.n_erasures == 0) || span == 0)
+      continue;
     const int wide = c.state_bytes() == 8;
     GroupPlan &gp = plan[wide];
     const int k = c.k(), m = c.m();
@@ -325,9 +337,10 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     for (uint64_t off = 0; off < st.block_bytes; off += kMaxPieceBytes) {
       StripeDesc d{};
       d.block_bytes = std::min<uint64_t>(kMaxPieceBytes, st.block_bytes - off);
-      d.k = k;
+      // update: the LFSR starts at the highest changed block
+      d.k = span;
       d.m = m;
-      d.k_pad = (k + c.state_bytes() - 1) / c.state_bytes() * c.state_bytes();
+      d.k_pad = (span + c.state_bytes() - 1) / c.state_bytes() * c.state_bytes();
       d.ptr_off = gp.ptrs.size();
       d.lfsr_set = lset;
       d.apply_set = aset;
@@ -336,6 +349,11 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
         d.n_out = m;
         for (int j = 0; j < k; ++j) gp.ptrs.push_back(at(j));
         for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(0);
+        for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
+      } else if (op == RS_POLY_OP_UPDATE) {
+        d.n_out = m;
+        for (int j = 0; j < span; ++j) gp.ptrs.push_back(st.blocks[j] ? at(j) : 0);
+        for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
         for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
       } else {
         const int t = st.n_erasures;
@@ -547,6 +565,13 @@ int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, in
   return b->run(RS_POLY_OP_DECODE, stripes, count, stream);
 }
 
+int rs_poly_batch_update(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, int count,
+                         void *stream) {
+  if (!b) return RS_ENULL;
+  std::lock_guard<std::mutex> lock(b->mu);
+  return b->run(RS_POLY_OP_UPDATE, stripes, count, stream);
+}
+
 int rs_poly_batch_get_launch(const rs_poly_batch_t *b, int op, int wide, rs_poly_launch_t *cfg) {
   if (!b || !cfg) return RS_ENULL;
   if (op < 0 || op >= kOps || wide < 0 || wide >= kWidths) return RS_EINVAL;
@@ -566,7 +591,7 @@ int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide, const rs_poly
 int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, int count,
                  void *stream, rs_poly_launch_t *best) {
   if (!b) return RS_ENULL;
-  if (op != RS_POLY_OP_ENCODE && op != RS_POLY_OP_DECODE) return RS_EINVAL;
+  if (op < 0 || op >= kOps) return RS_EINVAL;
   if (count < 0) return RS_EINVAL;
   if (count > 0 && !stripes) return RS_ENULL;
   std::lock_guard<std::mutex> lock(b->mu);
@@ -608,7 +633,8 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
             const rs_poly_launch_t c{bpl, th, tile, wgs};
             if (!valid_launch(op, w, c)) continue;
             b->launch[op][w] = c;
-            // one warm-up (also captures the graph), then 3 timed runs
+            // one warm-up (also captures the graph), then 3 timed runs: an
+            // even count, so an update leaves the parity as it found it
             double ms = 0;
             for (int rep = 0; rep < 4 && status == RS_OK; ++rep) {
               if (rep == 1) (void)hipEventRecord(e0, st);

@@ -32,6 +32,12 @@
 // computed once per pattern on the host: Opt3), applied as m packed product
 // lookups, one per remainder byte (region-level multiply-XOR: Opt4).
 //
+// Update = the update property of Sec. 3.2: encoding is linear, so new
+// parity = old parity + encode(delta), delta = new data - old data.  It is
+// the encode LFSR over the delta blocks (unchanged blocks are zero), then
+// the old parity is XORed in as decode does, and the result overwrites the
+// parity in place: one read-modify-write pass.
+//
 // LDS tables.  Each table is a GF(2)-linear map of one byte, expanded by
 // every workgroup from 8 basis values passed in the kernel arguments.  Entry
 // e of every table sits at byte e*256 (plus a per-table offset, an
@@ -102,13 +108,13 @@ __device__ __forceinline__ void st4(uint8_t *lds, uint32_t off, uint32_t a, uint
 }
 
 // LDS row layout.  Row e (256 bytes at e*256) holds entry e of every table.
-// Encode: 4 rotated copies of T', each kLfsrReps replicas wide.  Decode: the
+// Encode and update: 4 rotated copies of T', each kLfsrReps replicas wide.  Decode: the
 // same 4 copies at half the replication in bytes 0..127, and the apply
 // tables U'_b (one per remainder byte) in bytes 128..255.
 template <int M, int MODE>
 struct Layout {
   static constexpr uint32_t kEntry = M == 4 ? 4 : 8;              // bytes per value
-  static constexpr uint32_t kLfsrReps = (MODE == kEncode ? 256 : 128) / (4 * kEntry);
+  static constexpr uint32_t kLfsrReps = (MODE == kDecode ? 128 : 256) / (4 * kEntry);
   static constexpr uint32_t kCopyBytes = kLfsrReps * kEntry;      // one rotated copy
   static constexpr uint32_t kApplyReps = 128 / (M * kEntry);      // decode only
   static constexpr uint32_t kTableBytes = kApplyReps * kEntry;    // one apply table
@@ -358,20 +364,25 @@ struct TableSrc {
 };
 
 // Loads item g of a column chunk: for g < k_pad/M the M data blocks of LFSR
-// group g (window position q holds block k_pad-1-(g*M+q)); for decode, item
-// k_pad/M holds the parity read, position b holding p_(m-1-b).  Blocks not
+// group g (window position q holds block k_pad-1-(g*M+q)); for decode and
+// update, item k_pad/M holds the parity read, position b holding p_(m-1-b).  Blocks not
 // read (erased, unread, padding) give zeros.  In the vector form every slot
 // issues its load -- an absent block reads the zero page at an offset kept
 // inside it -- so the number of loads in flight never depends on the path
-// and the compiler can wait for exactly the item it is about to use.
+// and the compiler can wait for exactly the item it is about to use.  A
+// dummy item (the prefetch slot after a lane's last item) reads only the
+// zero page, which stays in cache: re-reading real blocks there would fetch
+// them from HBM a second time, since block loads do not keep lines in L2.
 template <int M, int W, int MODE, bool BYTEWISE, class Src>
 __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, int groups,
-                                          uint32_t (&a)[M][W]) {
+                                          bool dummy, uint32_t (&a)[M][W]) {
   const uint32_t B = src.B();
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const uint8_t *ptr;
-    if (MODE == kDecode && g == groups) {
+    if (dummy) {
+      ptr = nullptr;
+    } else if (MODE != kEncode && g == groups) {
       const int i = src.m() - 1 - q;
       ptr = i >= 0 ? src.par_in(i) : nullptr;
     } else {
@@ -433,10 +444,10 @@ __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lane
 }
 
 // After the last item of a chunk: byte b of the state is remainder
-// coefficient r_(m-1-b) (plus the parity read, for decode).  Decode maps it
-// through the apply tables; the result is transposed back to blocks and
-// stored: encode writes parity p_(m-1-b) from byte b, decode writes erased
-// block e from byte e.
+// coefficient r_(m-1-b) (plus the parity read, for decode and update).
+// Decode maps it through the apply tables; the result is transposed back to
+// blocks and stored: encode and update write parity p_(m-1-b) from byte b,
+// decode writes erased block e from byte e.
 template <int M, int W, int MODE, bool BYTEWISE, class Src>
 __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool active,
                                              uint32_t (&s)[4 * W][M / 4], const uint8_t *lds,
@@ -483,21 +494,22 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
       const int b = 4 * h + bb;
-      const int oi = MODE == kEncode ? m - 1 - b : b;
+      const int oi = MODE == kDecode ? b : m - 1 - b;
       if (oi >= 0 && oi < n_out && active)
         store_cols<W, BYTEWISE>(src.out(oi), col, src.B(), o[bb]);
     }
   }
 }
 
-// Encodes or decodes chunks c0 + (r*lanes + lane)*NC, r = 0, 1, ..., of one
-// stripe, for the n chunks starting at c0.  Control flow is uniform: every
-// lane runs the same rounds, and a lane whose chunk index is past n works on
-// chunk c0 again and stores nothing, so block pointers stay in SGPRs and
-// the loads need no branches.  The walk is a software pipeline over items
-// (LFSR groups, then for decode the parity item): the loads of the next
-// item, also across chunks, are issued before the current item goes through
-// the LFSR, so each lane keeps up to 2*M block loads in flight.
+// Encodes, updates or decodes chunks c0 + (r*lanes + lane)*NC, r = 0, 1,
+// ..., of one stripe, for the n chunks starting at c0.  Control flow is
+// uniform: every lane runs the same rounds, and a lane whose chunk index is
+// past n works on chunk c0 again and stores nothing, so block pointers stay
+// in SGPRs and the loads need no branches.  The walk is a software pipeline
+// over items (LFSR groups, then for decode and update the parity item): the
+// loads of the next item, also across chunks, are issued before the current
+// item goes through the LFSR, so each lane keeps up to 2*M block loads in
+// flight.  A chunk's parity is read (update) before the same lane writes it.
 template <int M, int W, int MODE, bool BYTEWISE, class Src>
 __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uint32_t n,
                                                 uint32_t lane, uint32_t lanes,
@@ -505,7 +517,7 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
   constexpr uint32_t NC = 4 * W;
   if (n == 0) return;
   const int groups = src.k_pad() / M;
-  const int items = groups + (MODE == kDecode ? 1 : 0);
+  const int items = groups + (MODE == kEncode ? 0 : 1);
   const uint32_t rounds = (n + lanes - 1) / lanes;
   auto col_of = [&](uint32_t r) {
     const uint32_t idx = r * lanes + lane;
@@ -521,7 +533,7 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
 
   uint32_t r = 0;   // round of the current item (uniform)
   int g = 0;        // item within the chunk (uniform)
-  load_item<M, W, MODE, BYTEWISE>(src, col_of(0), 0, groups, a);
+  load_item<M, W, MODE, BYTEWISE>(src, col_of(0), 0, groups, false, a);
 
   // One pipeline stage: prefetch the item after (r, g) into nxt, consume cur.
   auto stage = [&](uint32_t (&cur)[M][W], uint32_t (&nxt)[M][W]) -> bool {
@@ -532,8 +544,9 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
       ++nr;
     }
     const bool more = nr < rounds;
-    // past the last item the prefetch repeats the current one (and is unused)
-    load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, nxt);
+    // past the last item the prefetch is a dummy (and is unused)
+    load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, !more,
+                                    nxt);
     absorb_item<M, W, MODE>(s, cur, g < groups, lds, t);
     if (g == groups - 1) unrotate<M, W, MODE>(s, t);
     if (g == items - 1) {
@@ -720,8 +733,9 @@ int codec_max_threads(int sb, int dwords_per_lane) {
 }
 
 int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, void *stream) {
-  KernelFn fn = mode == kEncode ? pick<kEncode>(sb, cfg.dwords_per_lane, cfg.bytewise)
-                                : pick<kDecode>(sb, cfg.dwords_per_lane, cfg.bytewise);
+  KernelFn fn = mode == kEncode   ? pick<kEncode>(sb, cfg.dwords_per_lane, cfg.bytewise)
+                : mode == kDecode ? pick<kDecode>(sb, cfg.dwords_per_lane, cfg.bytewise)
+                                  : pick<kUpdate>(sb, cfg.dwords_per_lane, cfg.bytewise);
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0,
                      reinterpret_cast<hipStream_t>(stream), p);
   return (int)hipGetLastError();
@@ -736,8 +750,9 @@ int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
                      0, st, g);
   int err = (int)hipGetLastError();
   if (err) return err;
-  BatchFn fn = mode == kEncode ? pick_batch<kEncode>(sb, cfg.dwords_per_lane)
-                               : pick_batch<kDecode>(sb, cfg.dwords_per_lane);
+  BatchFn fn = mode == kEncode   ? pick_batch<kEncode>(sb, cfg.dwords_per_lane)
+               : mode == kDecode ? pick_batch<kDecode>(sb, cfg.dwords_per_lane)
+                                 : pick_batch<kUpdate>(sb, cfg.dwords_per_lane);
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0, st, g);
   return (int)hipGetLastError();
 }

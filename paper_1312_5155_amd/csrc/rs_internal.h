@@ -39,8 +39,8 @@ constexpr uint32_t kZeroPageBytes = 65536;
 // Kernel arguments, passed by value (about 2.8 KiB, within the kernarg limit).
 struct CodecParams {
   const uint8_t *data[kMaxN];     // d_j; nullptr = symbol 0, not read
-  const uint8_t *par_in[kMaxM];   // decode: parity p_i read back, or nullptr
-  uint8_t *out[kMaxM];            // encode: p_i; decode: i-th erased block
+  const uint8_t *par_in[kMaxM];   // decode/update: parity p_i read back, or nullptr
+  uint8_t *out[kMaxM];            // encode/update: p_i; decode: i-th erased block
   uint64_t block_bytes;           // <= kMaxPieceBytes
   int32_t k;                      // data blocks
   int32_t m;                      // parity symbols (remainder bytes)
@@ -51,7 +51,9 @@ struct CodecParams {
   uint32_t apply_basis[kMaxM][16];// decode: per remainder byte, 8 values
 };
 
-enum Mode : int { kEncode = 0, kDecode = 1 };
+// kUpdate: parity ^= encode(delta) -- the encode LFSR over the changed data
+// blocks, plus the old parity read back in place.
+enum Mode : int { kEncode = 0, kDecode = 1, kUpdate = 2 };
 
 // A launch configuration of the codec kernel.
 struct LaunchCfg {

@@ -34,6 +34,12 @@ int validate_erasures(const Code &c, const int *e, int t, unsigned flags, int *s
 // Kernel arguments for the column range [offset, offset + B) of a stripe.
 void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *const *parity,
                         uint64_t offset, uint64_t B, CodecParams *p);
+// Delta-parity update: data slots j < span (one past the highest changed
+// block) hold the delta blocks or nullptr, parity is read and written in
+// place.
+int update_span(const Code &c, const uint8_t *const *delta);
+void fill_update_params(const Code &c, const uint8_t *const *delta, uint8_t *const *parity,
+                        int span, uint64_t offset, uint64_t B, CodecParams *p);
 void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
                         const int *sorted, int t, uint64_t offset, uint64_t B,
                         CodecParams *p);

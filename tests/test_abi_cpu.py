@@ -107,6 +107,15 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_encode(h, None, p, 16, None) == B.RS_ENULL
     p[2] = None
     assert lib.rs_poly_encode(h, d, p, 16, None) == B.RS_ENULL
+    # update: NULL delta entries are unchanged blocks; parity is required
+    nod = (ctypes.c_void_p * 10)()
+    p2 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
+    assert lib.rs_poly_update(h, nod, p2, 4096, None) == B.RS_OK   # nothing changed
+    assert lib.rs_poly_update(h, d, p2, 0, None) == B.RS_OK        # empty
+    assert lib.rs_poly_update(h, None, p2, 16, None) == B.RS_ENULL
+    assert lib.rs_poly_update(h, d, None, 16, None) == B.RS_ENULL
+    assert lib.rs_poly_update(None, d, p2, 16, None) == B.RS_ENULL
+    assert lib.rs_poly_update(h, nod, p, 16, None) == B.RS_ENULL   # p[2] is NULL
 
 
 def apply_plan_on_cpu(F, k, m, full, erasures, flags, code):

@@ -1,0 +1,281 @@
+"""GPU parity of the delta-parity update (the update property of Sec. 3.2):
+after an update with delta = new data XOR old data, the parity equals the
+oracle's encoding of the new data, byte for byte, on the plain and the
+batched path.  The starting parity is the oracle's encoding of the old
+data, so no GPU encode is involved."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_1312_5155_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FIELD = {}
+
+
+def field(w=8, poly=0x11D):
+    if (w, poly) not in FIELD:
+        FIELD[(w, poly)] = oracle.Field(w, poly)
+    return FIELD[(w, poly)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class UpdateCase:
+    """Old and new data of one stripe (host), the oracle's parity of the old
+    data, and device buffers for the delta blocks and the parity.  Blocks
+    are rows of buffers with a `pad`-byte gap (guard bytes) starting
+    `offset` bytes in."""
+
+    def __init__(self, k, m, nbytes, changed, seed, w=8, poly=0x11D, offset=0, pad=64):
+        self.k, self.m, self.n, self.changed = k, m, nbytes, sorted(changed)
+        mask = (1 << w) - 1
+        self.F = field(w, poly)
+        self.old = workloads.random_bytes(seed, (k, nbytes)) & mask
+        self.new = self.old.copy()
+        fresh = workloads.random_bytes(seed + 1, (k, nbytes)) & mask
+        for j in self.changed:
+            self.new[j] = fresh[j]
+        self.parity0 = oracle.encode(self.F, k, m, self.old)
+        self.stride = nbytes + pad
+        self.offset = offset
+        self.dbuf = torch.zeros(k * self.stride + offset + 64, dtype=torch.uint8, device="cuda")
+        self.pbuf = torch.full((m * self.stride + offset + 64,), 0xA5, dtype=torch.uint8,
+                               device="cuda")
+        for j in self.changed:
+            o = offset + j * self.stride
+            self.dbuf[o:o + nbytes] = torch.from_numpy(self.old[j] ^ self.new[j])
+        for i in range(m):
+            o = offset + i * self.stride
+            self.pbuf[o:o + nbytes] = torch.from_numpy(self.parity0[i])
+
+    def delta_ptrs(self):
+        base = self.dbuf.data_ptr() + self.offset
+        return [base + j * self.stride if j in self.changed else None for j in range(self.k)]
+
+    def parity_ptrs(self):
+        base = self.pbuf.data_ptr() + self.offset
+        return [base + i * self.stride for i in range(self.m)]
+
+    def parity(self):
+        host = self.pbuf.cpu().numpy()
+        rows = [host[self.offset + i * self.stride: self.offset + i * self.stride + self.n]
+                for i in range(self.m)]
+        return np.stack(rows), host
+
+    def check(self, want=None):
+        got, host = self.parity()
+        want = oracle.encode(self.F, self.k, self.m, self.new) if want is None else want
+        assert np.array_equal(got, want), (self.k, self.m, self.n, self.changed)
+        # guard bytes between and around the parity blocks are untouched
+        for i in range(self.m):
+            end = self.offset + i * self.stride + self.n
+            assert (host[end:end + (self.stride - self.n)] == 0xA5).all()
+        assert (host[:self.offset] == 0xA5).all()
+
+
+PLAIN = [(10, 4, 100003, [0]), (10, 4, 100003, [9]), (10, 4, 65536, [3, 7]),
+         (10, 4, 4097, list(range(10))), (6, 3, 17, [5]), (6, 3, 65536, [0, 2, 4]),
+         (12, 4, 8191, [11]), (32, 8, 70001, [0, 31]), (32, 8, 8192, [12]),
+         (5, 6, 1000, [1, 2]), (1, 1, 1, [0]), (13, 1, 999, [12]), (3, 7, 333, [0]),
+         (247, 8, 64, [100, 246]), (200, 4, 129, [0, 1, 2, 3, 4, 199])]
+
+
+@pytest.mark.parametrize("k,m,nbytes,changed", PLAIN)
+def test_update_matches_oracle_encode_of_new_data(k, m, nbytes, changed):
+    say(f"update k={k} m={m} B={nbytes} changed={changed}")
+    case = UpdateCase(k, m, nbytes, changed, seed=k * 131 + m * 17 + nbytes)
+    code = B.Code(k, m)
+    B.rs_poly_update(code.handle, case.delta_ptrs(), case.parity_ptrs(), nbytes)
+    torch.cuda.synchronize()
+    case.check()
+
+
+@pytest.mark.parametrize("offset", [1, 2, 4, 8])
+def test_update_misaligned_blocks(offset):
+    say(f"update misaligned offset={offset}")
+    case = UpdateCase(10, 4, 20001, [2, 6], seed=900 + offset, offset=offset, pad=3)
+    code = B.Code(10, 4)
+    code.update(case.delta_ptrs(), case.parity_ptrs(), 20001)
+    torch.cuda.synchronize()
+    case.check()
+
+
+def test_update_twice_restores_parity():
+    say("update twice")
+    case = UpdateCase(10, 4, 1 << 16, [1, 8], seed=41)
+    code = B.Code(10, 4)
+    for _ in range(2):
+        code.update(case.delta_ptrs(), case.parity_ptrs(), 1 << 16)
+    torch.cuda.synchronize()
+    case.check(want=case.parity0)
+
+
+def test_update_with_no_changed_block_is_a_noop():
+    case = UpdateCase(10, 4, 4096, [], seed=42)
+    code = B.Code(10, 4)
+    code.update(case.delta_ptrs(), case.parity_ptrs(), 4096)
+    torch.cuda.synchronize()
+    case.check(want=case.parity0)
+
+
+def test_update_gf16():
+    say("update GF(2^4)")
+    for (k, m, changed) in ((4, 3, [0]), (9, 5, [3, 8]), (12, 3, [11])):
+        case = UpdateCase(k, m, 777, changed, seed=k * 7 + m, w=4, poly=0x13)
+        code = B.Code(k, m, 4, 0x13)
+        code.update(case.delta_ptrs(), case.parity_ptrs(), 777)
+        torch.cuda.synchronize()
+        case.check()
+
+
+def test_update_sequence_tracks_the_data():
+    # Several rounds of random changes: the parity always equals the
+    # encoding of the current data.
+    say("update sequence")
+    k, m, nbytes = 12, 4, 50000
+    F = field()
+    rng = workloads.meta_rng(4242)
+    data = workloads.random_bytes(4243, (k, nbytes))
+    parity = torch.from_numpy(oracle.encode(F, k, m, data)).cuda()
+    dbuf = torch.zeros((k, nbytes), dtype=torch.uint8, device="cuda")
+    code = B.Code(k, m)
+    for r in range(6):
+        changed = sorted(rng.choice(k, size=int(rng.integers(1, 4)), replace=False).tolist())
+        fresh = workloads.random_bytes(5000 + r, (k, nbytes))
+        new = data.copy()
+        for j in changed:
+            new[j] = fresh[j]
+            dbuf[j] = torch.from_numpy(data[j] ^ new[j])
+        code.update([dbuf[j] if j in changed else None for j in range(k)],
+                    [parity[i] for i in range(m)], nbytes)
+        data = new
+    torch.cuda.synchronize()
+    assert np.array_equal(parity.cpu().numpy(), oracle.encode(F, k, m, data))
+
+
+# ------------------------------------------------------------- batched --
+
+def batch_cases(seed, count, codes, lo, hi):
+    rng = workloads.meta_rng(seed)
+    sizes = workloads.log_uniform_sizes(rng, count, lo, hi)
+    cases = []
+    for s in range(count):
+        k, m = codes[int(rng.integers(0, len(codes)))]
+        n_changed = int(rng.integers(0, k + 1))
+        changed = rng.choice(k, size=n_changed, replace=False).tolist()
+        # 256-byte aligned rows (the batch path needs 16-byte alignment)
+        cases.append(UpdateCase(k, m, int(sizes[s]), changed, seed=seed * 1000 + s,
+                                pad=(-int(sizes[s])) % 256 + 256))
+    return cases
+
+
+CODES = {}
+
+
+def code(k, m):
+    if (k, m) not in CODES:
+        CODES[(k, m)] = B.Code(k, m)
+    return CODES[(k, m)]
+
+
+def entries(cases):
+    return [(code(c.k, c.m), c.delta_ptrs() + c.parity_ptrs(), c.n) for c in cases]
+
+
+def test_batch_update_mixed_matches_oracle():
+    say("batch update mixed 40 stripes")
+    cases = batch_cases(61, 40, ((6, 3), (10, 4), (12, 4), (32, 8), (5, 6), (3, 1)),
+                        1, 300000)
+    bt = B.Batch()
+    bt.update(entries(cases))
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check()
+
+
+def test_batch_update_equals_plain_update():
+    say("batch update vs plain")
+    cases = batch_cases(62, 12, ((10, 4), (32, 8)), 4096, 1 << 20)
+    twins = batch_cases(62, 12, ((10, 4), (32, 8)), 4096, 1 << 20)
+    B.Batch().update(entries(cases))
+    for c in twins:
+        code(c.k, c.m).update(c.delta_ptrs(), c.parity_ptrs(), c.n)
+    torch.cuda.synchronize()
+    for a, b in zip(cases, twins):
+        assert np.array_equal(a.parity()[0], b.parity()[0])
+
+
+def test_batch_update_tune_leaves_parity_unchanged(tmp_path, monkeypatch):
+    say("batch update autotuner")
+    monkeypatch.setenv("RS_POLY_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    cases = batch_cases(63, 6, ((10, 4),), 1 << 16, 1 << 18)
+    bt = B.Batch()
+    best = bt.tune(B.RS_POLY_OP_UPDATE, entries(cases))
+    torch.cuda.synchronize()
+    assert best.bytes_per_lane in (4, 8, 16)
+    assert '"op": 2' in (tmp_path / "tune.jsonl").read_text()
+    for c in cases:
+        c.check(want=c.parity0)
+    bt.update(entries(cases))
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check()
+
+
+def test_batch_update_rejects_bad_input():
+    cases = batch_cases(64, 2, ((10, 4),), 4096, 8192)
+    bt = B.Batch()
+    ents = entries(cases)
+    bad = [(ents[0][0], ents[0][1][:10] + [None] + ents[0][1][11:], ents[0][2])]
+    with pytest.raises(B.RsPolyError) as ei:
+        bt.update(bad + ents[1:])
+    assert ei.value.code == B.RS_ENULL
+    odd = list(ents[0][1])
+    odd[10] += 1                     # parity not 16-byte aligned
+    with pytest.raises(B.RsPolyError) as ei:
+        bt.update([(ents[0][0], odd, ents[0][2])])
+    assert ei.value.code == B.RS_EINVAL
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check(want=c.parity0)      # nothing ran
+
+
+def test_full_size_rs104_256x1MiB_batch_update():
+    # One changed block per stripe of the 256 x 10 x 1 MiB workload; the
+    # oracle checks a column window of sampled stripes.
+    say("full size batch update RS(10,4) 256 x 1 MiB")
+    k, m, nbytes, S = 10, 4, 1 << 20, 256
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.data_seed(1) + 77)
+    old = torch.randint(0, 256, (S, k, nbytes), dtype=torch.uint8, device="cuda", generator=gen)
+    par = torch.empty((S, m, nbytes), dtype=torch.uint8, device="cuda")
+    c = code(k, m)
+    bt = B.Batch()
+    bt.encode([(c, [old[s, j].data_ptr() for j in range(k)] +
+                [par[s, i].data_ptr() for i in range(m)], nbytes) for s in range(S)])
+    rng = workloads.meta_rng(workloads.meta_seed(1) + 77)
+    changed = rng.integers(0, k, size=S)
+    delta = torch.randint(0, 256, (S, nbytes), dtype=torch.uint8, device="cuda", generator=gen)
+    ents = []
+    for s in range(S):
+        ptrs = [None] * k + [par[s, i].data_ptr() for i in range(m)]
+        ptrs[int(changed[s])] = delta[s].data_ptr()
+        ents.append((c, ptrs, nbytes))
+    bt.update(ents)
+    torch.cuda.synchronize()
+    F = field()
+    for s in (0, 1, 100, 255):
+        lo, hi = (s * 4099) % (nbytes - 65536), (s * 4099) % (nbytes - 65536) + 65536
+        d = old[s, :, lo:hi].cpu().numpy().copy()
+        d[int(changed[s])] ^= delta[s, lo:hi].cpu().numpy()
+        assert np.array_equal(par[s, :, lo:hi].cpu().numpy(), oracle.encode(F, k, m, d)), s
