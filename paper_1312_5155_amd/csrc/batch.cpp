@@ -47,26 +47,32 @@ struct GraphEntry {
 bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
   if (c.bytes_per_lane != 4 && c.bytes_per_lane != 8 && c.bytes_per_lane != 16) return false;
   if (c.threads != 256 && c.threads != 512 && c.threads != 1024) return false;
-  if (c.threads > codec_max_threads(wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
+  const Mode mode = op == RS_POLY_OP_DECODE ? kDecode : op == RS_POLY_OP_UPDATE ? kUpdate : kEncode;
+  if (c.threads > codec_max_threads(mode, wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
   if (c.tile_bytes < 4096 || c.tile_bytes % 16 != 0) return false;
-  (void)op;
   return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 2;
 }
 
-// Defaults from a sweep of every shape on RS(10,4), 256 x 1 MiB stripes,
-// MI355X (the autotuner refines them per workload).
+// Defaults from sweeps of every shape on RS(10,4), 256 x 1 MiB stripes (and
+// RS(32,8) for wide codes), MI355X; the autotuner refines them per workload.
 rs_poly_launch_t default_launch(int op, int wide) {
   rs_poly_launch_t c;
   if (op != RS_POLY_OP_DECODE && !wide) {
     c.bytes_per_lane = 8;
     c.threads = 1024;
     c.tile_bytes = 16 << 10;
+  } else if (wide) {
+    // RS(32,8), 64 x 32 x 4 MiB stripes
+    c.bytes_per_lane = op == RS_POLY_OP_DECODE ? 4 : 8;
+    c.threads = 1024;
+    c.tile_bytes = op == RS_POLY_OP_DECODE ? 256 << 10 : 64 << 10;
   } else {
     c.bytes_per_lane = 16;
-    c.threads = wide ? 256 : 512;
-    c.tile_bytes = wide ? 64 << 10 : 16 << 10;
+    c.threads = 512;
+    c.tile_bytes = 16 << 10;
   }
-  c.wgs_per_cu = 2;
+  // (a wide decode workgroup takes 128 KiB of LDS: one fits per CU)
+  c.wgs_per_cu = op == RS_POLY_OP_DECODE && wide ? 1 : 2;
   return c;
 }
 

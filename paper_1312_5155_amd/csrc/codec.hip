@@ -18,9 +18,8 @@
 //   * the shift is removed by letting byte positions rotate: the register
 //     holds P = rotl(u, 8t) at step t, the feedback byte is byte (t mod M) of
 //     P, and P' = P ^ rotl(T'[f], 8(t+1)) with T'[f] = T[f] ^ (f << 8(M-1))
-//     (the extra term clears the consumed byte).  The rotated copies of T'
-//     are separate LDS tables; for M = 8 rotations by 4 bytes are free (swap
-//     the two dwords), so 4 copies serve 8 positions.
+//     (the extra term clears the consumed byte).  The M rotated copies of
+//     T' are separate LDS tables.
 // k is padded at the top to a multiple of M with zero symbols (leading zeros
 // leave a zero remainder unchanged), so the rotation is back at 0 at the end.
 //
@@ -40,10 +39,12 @@
 //
 // LDS tables.  Each table is a GF(2)-linear map of one byte, expanded by
 // every workgroup from 8 basis values passed in the kernel arguments.  Entry
-// e of every table sits at byte e*256 (plus a per-table offset, an
-// immediate of the LDS read, and a per-lane replica), so one v_perm_b32 of
-// (state, lane offset) yields the address; replicas spread the lanes of a
-// wave over banks.  64 KiB per workgroup, two workgroups per CU.
+// e of every table sits at byte e*256 plus the table's offset and the
+// lane's replica offset, so one v_perm_b32 of (state, lane offset) yields
+// the address (M = 4; a v_perm and an OR for M = 8).  Replicas spread the
+// lanes of a wave over banks, and lanes start at different rotation phases,
+// so that one read spreads over all copies.  64 KiB per workgroup, two workgroups
+// per CU (128 KiB and one workgroup for the decode of m > 4).
 //
 // Memory-level parallelism.  The kernels stream every byte once; throughput
 // is set by the bytes in flight per CU.  Each lane walks its column chunks
@@ -107,22 +108,32 @@ __device__ __forceinline__ void st4(uint8_t *lds, uint32_t off, uint32_t a, uint
   *reinterpret_cast<uint4 *>(lds + off) = make_uint4(a, b, c, d);
 }
 
-// LDS row layout.  Row e (256 bytes at e*256) holds entry e of every table.
-// Encode and update: 4 rotated copies of T', each kLfsrReps replicas wide.  Decode: the
-// same 4 copies at half the replication in bytes 0..127, and the apply
-// tables U'_b (one per remainder byte) in bytes 128..255.
+// LDS row layout.  Row e (256 bytes at e*256) holds entry e of every table;
+// a row spans the 64 banks once, so a lane's bank is set by its offset in
+// the row alone.  LDS serves a wave's read in passes of 32 lanes, and a
+// read is conflict-free when the 32 lanes of a pass use distinct banks.
+// Encode and update: the M rotated copies of T' (copy v = rotation by v+1
+// bytes), each kLfsrReps replicas wide.  Decode of m <= 4: the same copies
+// at half the replication in bytes 0..127 and the apply tables U'_b (one
+// per remainder byte) in bytes 128..255.  Decode of m > 4 (8-byte entries)
+// needs whole rows for both, so its apply tables sit in a second 64 KiB
+// region (128 KiB of LDS, one workgroup per CU).
 template <int M, int MODE>
 struct Layout {
+  static constexpr bool kTwoRegions = M == 8 && MODE == kDecode;
   static constexpr uint32_t kEntry = M == 4 ? 4 : 8;              // bytes per value
-  static constexpr uint32_t kLfsrReps = (MODE == kDecode ? 128 : 256) / (4 * kEntry);
+  static constexpr uint32_t kCopies = M;                          // rotations 1..M bytes
+  static constexpr uint32_t kLfsrReps =
+      (MODE == kDecode && !kTwoRegions ? 128 : 256) / (kCopies * kEntry);
   static constexpr uint32_t kCopyBytes = kLfsrReps * kEntry;      // one rotated copy
-  static constexpr uint32_t kApplyReps = 128 / (M * kEntry);      // decode only
+  static constexpr uint32_t kApplyReps = (kTwoRegions ? 256 : 128) / (M * kEntry);
   static constexpr uint32_t kTableBytes = kApplyReps * kEntry;    // one apply table
-  static constexpr uint32_t kApplyBase = 128;
-  // Lane groups at different rotation phases (m <= 4 only): in one LDS read
-  // group g uses copy (q + g) mod 4, so the copies' replicas together cover
-  // all 32 banks.
-  static constexpr uint32_t kPhases = M == 4 ? 32 / kLfsrReps : 1;
+  static constexpr uint32_t kApplyBase = kTwoRegions ? 65536 : 128;
+  static constexpr uint32_t kLdsBytes = kTwoRegions ? 131072 : 65536;
+  // Lane groups at different rotation phases: in one LDS read group g uses
+  // copy (q + g) mod M, so the 32 lanes of a pass cover 32 distinct
+  // replica slots (banks).
+  static constexpr uint32_t kPhases = M == 4 ? 32 / kLfsrReps : 8;
 };
 
 // Per-lane LDS addressing, computed once per kernel.  A lane of phase g keeps
@@ -130,10 +141,16 @@ struct Layout {
 // step q it reads feedback byte (q + g) mod 4 from copy (q + g) mod 4.  Data
 // enter rotated by g bytes and the state leaves un-rotated.  Decode lanes
 // likewise walk the apply tables in rotated order.
+//
+// M = 8: the state is two dwords, and byte (q + g) mod 8 may sit in either,
+// so a step selects it with a v_perm over both dwords and ORs in the lane
+// offset; rotations into and out of the phase are v_perm byte shuffles of
+// the dword pair.
 template <int M, int MODE>
 struct Lanes {
-  uint32_t lsel[4], loff[4];   // LFSR step q: v_perm selector, byte offset
-  uint32_t rot_in, rot_out;    // v_alignbit shifts into / out of the phase
+  uint32_t lsel[M], loff[M];   // LFSR step q: v_perm selector, byte offset
+  uint32_t rot_in, rot_out;    // M = 4: v_alignbit shifts into / out of the phase
+  uint32_t rin[2], rout[2];    // M = 8: v_perm selectors (low, high dword)
   uint32_t asel[M], aoff[M];   // decode apply, slot b
 };
 
@@ -145,32 +162,44 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
   const uint32_t g = (lane / L::kLfsrReps) % L::kPhases;
   const uint32_t rep = lane & (L::kLfsrReps - 1);
 #pragma unroll
-  for (uint32_t q = 0; q < 4; ++q) {
-    const uint32_t p = (q + g) & 3;
-    t.lsel[q] = 0x0C0C0400u | (p << 8);
+  for (uint32_t q = 0; q < (uint32_t)M; ++q) {
+    const uint32_t p = (q + g) & (M - 1);
+    // M = 4: byte 1 <- state byte p, byte 0 <- lane offset.  M = 8: byte 1
+    // <- byte p of the dword pair (selector p: 0..3 low dword, 4..7 high).
+    t.lsel[q] = M == 4 ? 0x0C0C0400u | (p << 8) : 0x0C0C000Cu | (p << 8);
     t.loff[q] = p * L::kCopyBytes + rep * L::kEntry;
   }
   t.rot_in = (32 - 8 * g) & 31;
   t.rot_out = 8 * g;
+  // M = 8: rotl64 by g bytes takes result byte i from byte (i - g) mod 8;
+  // the inverse from byte (i + g) mod 8.
+  t.rin[0] = t.rin[1] = t.rout[0] = t.rout[1] = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) {
+    t.rin[0] |= ((i - g) & 7) << (8 * i);
+    t.rin[1] |= ((i + 4 - g) & 7) << (8 * i);
+    t.rout[0] |= ((i + g) & 7) << (8 * i);
+    t.rout[1] |= ((i + 4 + g) & 7) << (8 * i);
+  }
   if constexpr (MODE == kDecode) {
     const uint32_t arep = lane & (L::kApplyReps - 1);
-    const uint32_t ga = M == 4 ? (lane / L::kApplyReps) % 4 : 0;
+    const uint32_t ga = (lane / L::kApplyReps) % M;
 #pragma unroll
     for (uint32_t b = 0; b < (uint32_t)M; ++b) {
-      const uint32_t tb = M == 4 ? (b + ga) & 3 : b;
-      t.asel[b] = 0x0C0C0400u | ((tb & 3) << 8);
+      const uint32_t tb = (b + ga) & (M - 1);
+      t.asel[b] = M == 4 ? 0x0C0C0400u | (tb << 8) : 0x0C0C000Cu | (tb << 8);
       t.aoff[b] = L::kApplyBase + tb * L::kTableBytes + arep * L::kEntry;
     }
   }
   return t;
 }
 
-// Expands the LFSR tables: copy v (0..3) of entry f is rotl(T'[f], 8(v+1)).
+// Expands the LFSR tables: copy v (0..M-1) of entry f is rotl(T'[f], 8(v+1)).
 template <int M, int MODE>
 __device__ void build_lfsr_tables(uint8_t *lds, const uint32_t *basis) {
   using L = Layout<M, MODE>;
-  for (uint32_t idx = threadIdx.x; idx < 1024; idx += blockDim.x) {
-    const uint32_t f = idx >> 2, v = idx & 3;
+  for (uint32_t idx = threadIdx.x; idx < 256 * L::kCopies; idx += blockDim.x) {
+    const uint32_t f = idx / L::kCopies, v = idx % L::kCopies;
     const uint32_t base = f * kRowBytes + v * L::kCopyBytes;
     uint32_t lo, hi;
     if constexpr (M == 4) {
@@ -285,21 +314,14 @@ __device__ __forceinline__ void store_cols(uint8_t *ptr, uint32_t col, uint32_t 
 template <int M, int MODE>
 __device__ __forceinline__ void lfsr_step(uint32_t (&s)[M / 4], const uint8_t *lds,
                                           const Lanes<M, MODE> &t, int q) {
-  const int bp = q & 3;
   if constexpr (M == 4) {
-    const uint32_t addr = perm(s[0], t.loff[bp], t.lsel[bp]);
+    const uint32_t addr = perm(s[0], t.loff[q], t.lsel[q]);
     s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
   } else {
-    const int half = q >> 2;
-    const uint32_t addr = perm(s[half], t.loff[bp], t.lsel[bp]);
+    const uint32_t addr = perm(s[1], s[0], t.lsel[q]) | t.loff[q];
     const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
-    if (half == 0) {
-      s[0] ^= v.x;
-      s[1] ^= v.y;
-    } else {
-      s[0] ^= v.y;
-      s[1] ^= v.x;
-    }
+    s[0] ^= v.x;
+    s[1] ^= v.y;
   }
 }
 
@@ -414,18 +436,26 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
   constexpr int NQ = M / 4;
   constexpr int NC = 4 * W;
 #pragma unroll
-  for (int w = 0; w < W; ++w)
+  for (int w = 0; w < W; ++w) {
+    uint32_t d[NQ][4];
 #pragma unroll
-    for (int h = 0; h < NQ; ++h) {
-      uint32_t d[4];
-      transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[0], d[1],
-                 d[2], d[3]);
+    for (int h = 0; h < NQ; ++h)
+      transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
+                 d[h][1], d[h][2], d[h][3]);
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        if (M == 4 && lfsr) d[x] = __builtin_amdgcn_alignbit(d[x], d[x], t.rot_in);
-        s[4 * w + x][h] ^= d[x];
+    for (int x = 0; x < 4; ++x) {
+      if constexpr (M == 4) {
+        if (lfsr) d[0][x] = __builtin_amdgcn_alignbit(d[0][x], d[0][x], t.rot_in);
+      } else if (lfsr) {
+        const uint32_t lo = perm(d[1][x], d[0][x], t.rin[0]);
+        const uint32_t hi = perm(d[1][x], d[0][x], t.rin[1]);
+        d[0][x] = lo;
+        d[1][x] = hi;
       }
+#pragma unroll
+      for (int h = 0; h < NQ; ++h) s[4 * w + x][h] ^= d[h][x];
     }
+  }
   if (lfsr) {
 #pragma unroll
     for (int q = 0; q < M; ++q)
@@ -437,9 +467,16 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
 // Brings the column states back from the lane's rotation phase.
 template <int M, int W, int MODE>
 __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lanes<M, MODE> &t) {
-  if constexpr (M == 4) {
 #pragma unroll
-    for (int c = 0; c < 4 * W; ++c) s[c][0] = __builtin_amdgcn_alignbit(s[c][0], s[c][0], t.rot_out);
+  for (int c = 0; c < 4 * W; ++c) {
+    if constexpr (M == 4) {
+      s[c][0] = __builtin_amdgcn_alignbit(s[c][0], s[c][0], t.rot_out);
+    } else {
+      const uint32_t lo = perm(s[c][1], s[c][0], t.rout[0]);
+      const uint32_t hi = perm(s[c][1], s[c][0], t.rout[1]);
+      s[c][0] = lo;
+      s[c][1] = hi;
+    }
   }
 }
 
@@ -456,33 +493,28 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
   constexpr int NC = 4 * W;
   const int m = src.m(), n_out = src.n_out();
   if constexpr (MODE == kDecode) {
-    uint32_t L[NC][NQ];   // packed rebuilt symbols
+    // Column by column (few live registers): every lane walks all M tables
+    // (those past m are zero) in its rotated order.
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      uint32_t L[NQ];   // packed rebuilt symbols
 #pragma unroll
-      for (int h = 0; h < NQ; ++h) L[c][h] = 0;
+      for (int h = 0; h < NQ; ++h) L[h] = 0;
 #pragma unroll
-    for (int b = 0; b < M; ++b) {
-      // m <= 4: every lane walks all 4 tables (those past m are zero) in its
-      // rotated order; m > 4: tables b < m in order.
-      if (M == 4 || b < m) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const uint32_t addr = perm(s[c][M == 4 ? 0 : b >> 2], t.aoff[b], t.asel[b]);
-          if constexpr (M == 4) {
-            L[c][0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
-          } else {
-            const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
-            L[c][0] ^= v.x;
-            L[c][1] ^= v.y;
-          }
+      for (int b = 0; b < M; ++b) {
+        if constexpr (M == 4) {
+          const uint32_t addr = perm(s[c][0], t.aoff[b], t.asel[b]);
+          L[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
+        } else {
+          const uint32_t addr = perm(s[c][1], s[c][0], t.asel[b]) | t.aoff[b];
+          const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
+          L[0] ^= v.x;
+          L[1] ^= v.y;
         }
       }
+#pragma unroll
+      for (int h = 0; h < NQ; ++h) s[c][h] = L[h];
     }
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int h = 0; h < NQ; ++h) s[c][h] = L[c][h];
   }
 #pragma unroll
   for (int h = 0; h < NQ; ++h) {
@@ -581,20 +613,21 @@ __device__ __forceinline__ void process_range(const Src &src, uint32_t c0, uint3
     process_columns<M, 1, MODE, true>(src, tail, (c1 - tail + 3) / 4, 0, 1, lds, t);
 }
 
-constexpr uint32_t kLdsBytes = 256 * kRowBytes;
-
 // Workgroup size bound per variant: the 16-byte-per-lane variants hold two
-// items of loads in flight and need more than 128 VGPRs.
-template <int M, int W>
+// items of loads in flight and need more than 128 VGPRs, and so does the
+// wide decode at 8 bytes per lane (its lane constants cover 8 rotations and
+// 8 apply tables).  The wide decode has no 16-byte variant.
+template <int M, int W, int MODE>
 constexpr int max_threads() {
+  if (M == 8 && MODE == kDecode) return W == 4 ? 0 : W == 2 ? 512 : 1024;
   return W == 4 ? (M == 8 ? 256 : 512) : 1024;
 }
 
 // One stripe per launch: grid-stride loop over its column chunks.
 template <int M, int W, int MODE, bool BYTEWISE>
-__global__ void __launch_bounds__((max_threads<M, W>()))
+__global__ void __launch_bounds__((max_threads<M, W, MODE>()))
 __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) codec_kernel(CodecParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[Layout<M, MODE>::kLdsBytes];
   build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
   if constexpr (MODE == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
   __syncthreads();
@@ -643,9 +676,9 @@ __global__ void batch_prepare_kernel(BatchGroup g) {
 // or decodes the tile's columns.  Every wave leaves the loop once the counter
 // passes the last tile.
 template <int M, int W, int MODE>
-__global__ void __launch_bounds__((max_threads<M, W>()))
+__global__ void __launch_bounds__((max_threads<M, W, MODE>()))
 __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[Layout<M, MODE>::kLdsBytes];
   __shared__ uint64_t next_tile;
   BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
   const_as<BatchHeader> chdr = as_const(hdr);
@@ -716,8 +749,10 @@ BatchFn pick_batch(int sb, int w) {
     if (w == 2) return batch_kernel<4, 2, MODE>;
     return batch_kernel<4, 1, MODE>;
   }
-  if (w == 4) return batch_kernel<8, 4, MODE>;
-  if (w == 2) return batch_kernel<8, 2, MODE>;
+  if constexpr (MODE != kDecode) {
+    if (w == 4) return batch_kernel<8, 4, MODE>;
+  }
+  if (w >= 2) return batch_kernel<8, 2, MODE>;
   return batch_kernel<8, 1, MODE>;
 }
 
@@ -727,7 +762,9 @@ int codec_wgs_per_cu(Mode) { return 2; }
 
 int codec_plain_max_dwords(int sb) { return sb == 8 ? 2 : 4; }
 
-int codec_max_threads(int sb, int dwords_per_lane) {
+int codec_max_threads(Mode mode, int sb, int dwords_per_lane) {
+  if (sb == 8 && mode == kDecode)
+    return dwords_per_lane == 4 ? 0 : dwords_per_lane == 2 ? 512 : 1024;
   if (dwords_per_lane == 4) return sb == 8 ? 256 : 512;
   return 1024;
 }

@@ -114,8 +114,9 @@ int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint64_t max_t
 
 // Resident workgroups per CU the kernel is sized for (LDS bound).
 int codec_wgs_per_cu(Mode mode);
-// Largest workgroup a variant is compiled for (register bound).
-int codec_max_threads(int state_bytes, int dwords_per_lane);
+// Largest workgroup a variant is compiled for (register bound); 0 if the
+// variant does not exist.
+int codec_max_threads(Mode mode, int state_bytes, int dwords_per_lane);
 // Widest loads (dwords per lane) of the one-stripe kernel for a state width.
 int codec_plain_max_dwords(int state_bytes);
 

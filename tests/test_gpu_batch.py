@@ -179,7 +179,10 @@ def test_every_launch_shape(bpl, threads):
         cfg = dict(bytes_per_lane=bpl, threads=th, tile_bytes=4096 * (1 + wide),
                    wgs_per_cu=1 + wide)
         bt.set_launch(B.RS_POLY_OP_ENCODE, wide, cfg)
-        bt.set_launch(B.RS_POLY_OP_DECODE, wide, cfg)
+        # the wide decode: at most 8 bytes per lane, 512 threads at 8
+        dbpl = min(bpl, 8) if wide else bpl
+        dth = min(th, 512) if wide and dbpl == 8 else th
+        bt.set_launch(B.RS_POLY_OP_DECODE, wide, dict(cfg, bytes_per_lane=dbpl, threads=dth))
     bt.encode(encode_entries(arena))
     torch.cuda.synchronize()
     check_encoded(arena, host)
@@ -211,6 +214,13 @@ def test_set_launch_validation():
         bt.set_launch(B.RS_POLY_OP_ENCODE, 1, dict(bytes_per_lane=16, threads=512,
                                                   tile_bytes=4096, wgs_per_cu=1))
     bt.set_launch(B.RS_POLY_OP_ENCODE, 1, dict(bytes_per_lane=8, threads=1024,
+                                              tile_bytes=4096, wgs_per_cu=2))
+    # the wide decode has no 16-byte variant and runs 8 bytes with <= 512
+    for bad_wide in (dict(bytes_per_lane=16, threads=256, tile_bytes=4096, wgs_per_cu=1),
+                     dict(bytes_per_lane=8, threads=1024, tile_bytes=4096, wgs_per_cu=1)):
+        with pytest.raises(B.RsPolyError):
+            bt.set_launch(B.RS_POLY_OP_DECODE, 1, bad_wide)
+    bt.set_launch(B.RS_POLY_OP_DECODE, 1, dict(bytes_per_lane=8, threads=512,
                                               tile_bytes=4096, wgs_per_cu=2))
 
 
