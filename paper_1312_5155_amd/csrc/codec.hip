@@ -71,18 +71,26 @@ __device__ __forceinline__ uint64_t rotl64(uint64_t x, int s) {
   return s ? (x << s) | (x >> (64 - s)) : x;
 }
 
-// 4x4 byte transpose: o_b = (i0.byte b, i1.byte b, i2.byte b, i3.byte b).
+// 4x4 byte transpose: o_b = (i0.byte b, i1.byte b, i2.byte b, i3.byte b),
+// as two rounds of v_perm.  Other selectors fold a byte rotation in: second
+// round selectors rotated left by 8g bytes give rotl(o_b, 8g); first round
+// selectors that read byte b + g give the transpose of inputs rotated by g.
+constexpr uint32_t kT1a = 0x05010400u, kT1b = 0x07030602u;   // first round
+constexpr uint32_t kT2a = 0x05040100u, kT2b = 0x07060302u;   // second round
+
 __device__ __forceinline__ void transpose4(uint32_t i0, uint32_t i1, uint32_t i2, uint32_t i3,
                                            uint32_t &o0, uint32_t &o1, uint32_t &o2,
-                                           uint32_t &o3) {
-  const uint32_t lo01 = perm(i1, i0, 0x05010400u);  // i0.b0 i1.b0 i0.b1 i1.b1
-  const uint32_t hi01 = perm(i1, i0, 0x07030602u);  // i0.b2 i1.b2 i0.b3 i1.b3
-  const uint32_t lo23 = perm(i3, i2, 0x05010400u);
-  const uint32_t hi23 = perm(i3, i2, 0x07030602u);
-  o0 = perm(lo23, lo01, 0x05040100u);
-  o1 = perm(lo23, lo01, 0x07060302u);
-  o2 = perm(hi23, hi01, 0x05040100u);
-  o3 = perm(hi23, hi01, 0x07060302u);
+                                           uint32_t &o3, uint32_t s1a = kT1a,
+                                           uint32_t s1b = kT1b, uint32_t s2a = kT2a,
+                                           uint32_t s2b = kT2b) {
+  const uint32_t lo01 = perm(i1, i0, s1a);  // i0.b0 i1.b0 i0.b1 i1.b1
+  const uint32_t hi01 = perm(i1, i0, s1b);  // i0.b2 i1.b2 i0.b3 i1.b3
+  const uint32_t lo23 = perm(i3, i2, s1a);
+  const uint32_t hi23 = perm(i3, i2, s1b);
+  o0 = perm(lo23, lo01, s2a);
+  o1 = perm(lo23, lo01, s2b);
+  o2 = perm(hi23, hi01, s2a);
+  o3 = perm(hi23, hi01, s2b);
 }
 
 // Image of byte f under the linear map with basis values basis[0..7].
@@ -138,9 +146,14 @@ struct Layout {
 
 // Per-lane LDS addressing, computed once per kernel.  A lane of phase g keeps
 // its state rotated by g more bytes than the step count says: at unrolled
-// step q it reads feedback byte (q + g) mod 4 from copy (q + g) mod 4.  Data
-// enter rotated by g bytes and the state leaves un-rotated.  Decode lanes
-// likewise walk the apply tables in rotated order.
+// step q it reads feedback byte (q + g) mod M from copy (q + g) mod M.
+// Decode lanes likewise walk the apply tables in rotated order.
+//
+// M = 4: the state stays rotated to the end of a chunk.  Items enter
+// rotated by g bytes through the second transpose round, decode reads the
+// apply index at byte (b + g) mod 4, and encode/update outputs leave
+// through a first transpose round that reads byte b + g: the rotation costs
+// no instruction.
 //
 // M = 8: the state is two dwords, and byte (q + g) mod 8 may sit in either,
 // so a step selects it with a v_perm over both dwords and ORs in the lane
@@ -149,7 +162,7 @@ struct Layout {
 template <int M, int MODE>
 struct Lanes {
   uint32_t lsel[M], loff[M];   // LFSR step q: v_perm selector, byte offset
-  uint32_t rot_in, rot_out;    // M = 4: v_alignbit shifts into / out of the phase
+  uint32_t tin[2], tout[2];    // M = 4: rotating transpose selectors (in, out)
   uint32_t rin[2], rout[2];    // M = 8: v_perm selectors (low, high dword)
   uint32_t asel[M], aoff[M];   // decode apply, slot b
 };
@@ -169,8 +182,14 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
     t.lsel[q] = M == 4 ? 0x0C0C0400u | (p << 8) : 0x0C0C000Cu | (p << 8);
     t.loff[q] = p * L::kCopyBytes + rep * L::kEntry;
   }
-  t.rot_in = (32 - 8 * g) & 31;
-  t.rot_out = 8 * g;
+  t.tin[0] = rotl32(kT2a, 8 * g);
+  t.tin[1] = rotl32(kT2b, 8 * g);
+  t.tout[0] = t.tout[1] = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 2; ++i) {
+    t.tout[0] |= (((i + g) & 3) | (((4 + ((i + g) & 3))) << 8)) << (16 * i);
+    t.tout[1] |= (((i + 2 + g) & 3) | (((4 + ((i + 2 + g) & 3))) << 8)) << (16 * i);
+  }
   // M = 8: rotl64 by g bytes takes result byte i from byte (i - g) mod 8;
   // the inverse from byte (i + g) mod 8.
   t.rin[0] = t.rin[1] = t.rout[0] = t.rout[1] = 0;
@@ -187,7 +206,8 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
 #pragma unroll
     for (uint32_t b = 0; b < (uint32_t)M; ++b) {
       const uint32_t tb = (b + ga) & (M - 1);
-      t.asel[b] = M == 4 ? 0x0C0C0400u | (tb << 8) : 0x0C0C000Cu | (tb << 8);
+      // M = 4: remainder byte tb sits at byte tb + g of the rotated state
+      t.asel[b] = M == 4 ? 0x0C0C0400u | (((tb + g) & 3) << 8) : 0x0C0C000Cu | (tb << 8);
       t.aoff[b] = L::kApplyBase + tb * L::kTableBytes + arep * L::kEntry;
     }
   }
@@ -427,11 +447,16 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
 }
 
 // XORs an item into the column states (transposed so that each column's M
-// symbols fill its state window; for an LFSR group rotated into the lane's
-// phase), then, for an LFSR group, runs its M steps.
+// symbols fill its state window, rotated into the lane's phase: for M = 8
+// only LFSR groups, since the state is brought back before the parity item),
+// then, for an LFSR group, runs its M steps.  The first `skip` steps are
+// left out: they are the leading window positions of the first group that
+// hold no block (padding or absent blocks above every present one), where
+// the state is still zero, so the feedback is zero and a step changes
+// nothing.
 template <int M, int W, int MODE>
 __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
-                                            bool lfsr, const uint8_t *lds,
+                                            bool lfsr, int skip, const uint8_t *lds,
                                             const Lanes<M, MODE> &t) {
   constexpr int NQ = M / 4;
   constexpr int NC = 4 * W;
@@ -439,18 +464,23 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
   for (int w = 0; w < W; ++w) {
     uint32_t d[NQ][4];
 #pragma unroll
-    for (int h = 0; h < NQ; ++h)
-      transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
-                 d[h][1], d[h][2], d[h][3]);
+    for (int h = 0; h < NQ; ++h) {
+      if constexpr (M == 4)
+        transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
+                   d[h][1], d[h][2], d[h][3], kT1a, kT1b, t.tin[0], t.tin[1]);
+      else
+        transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
+                   d[h][1], d[h][2], d[h][3]);
+    }
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      if constexpr (M == 4) {
-        if (lfsr) d[0][x] = __builtin_amdgcn_alignbit(d[0][x], d[0][x], t.rot_in);
-      } else if (lfsr) {
-        const uint32_t lo = perm(d[1][x], d[0][x], t.rin[0]);
-        const uint32_t hi = perm(d[1][x], d[0][x], t.rin[1]);
-        d[0][x] = lo;
-        d[1][x] = hi;
+      if constexpr (M == 8) {
+        if (lfsr) {
+          const uint32_t lo = perm(d[1][x], d[0][x], t.rin[0]);
+          const uint32_t hi = perm(d[1][x], d[0][x], t.rin[1]);
+          d[0][x] = lo;
+          d[1][x] = hi;
+        }
       }
 #pragma unroll
       for (int h = 0; h < NQ; ++h) s[4 * w + x][h] ^= d[h][x];
@@ -458,20 +488,21 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
   }
   if (lfsr) {
 #pragma unroll
-    for (int q = 0; q < M; ++q)
+    for (int q = 0; q < M; ++q) {
+      if (q < skip) continue;
 #pragma unroll
       for (int c = 0; c < NC; ++c) lfsr_step<M, MODE>(s[c], lds, t, q);
+    }
   }
 }
 
-// Brings the column states back from the lane's rotation phase.
+// M = 8: brings the column states back from the lane's rotation phase
+// (M = 4 keeps them rotated; see Lanes).
 template <int M, int W, int MODE>
 __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lanes<M, MODE> &t) {
+  if constexpr (M == 8) {
 #pragma unroll
-  for (int c = 0; c < 4 * W; ++c) {
-    if constexpr (M == 4) {
-      s[c][0] = __builtin_amdgcn_alignbit(s[c][0], s[c][0], t.rot_out);
-    } else {
+    for (int c = 0; c < 4 * W; ++c) {
       const uint32_t lo = perm(s[c][1], s[c][0], t.rout[0]);
       const uint32_t hi = perm(s[c][1], s[c][0], t.rout[1]);
       s[c][0] = lo;
@@ -481,7 +512,8 @@ __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lane
 }
 
 // After the last item of a chunk: byte b of the state is remainder
-// coefficient r_(m-1-b) (plus the parity read, for decode and update).
+// coefficient r_(m-1-b) (plus the parity read, for decode and update); for
+// M = 4 the state is still rotated by the lane's phase g (byte b at b + g).
 // Decode maps it through the apply tables; the result is transposed back to
 // blocks and stored: encode and update write parity p_(m-1-b) from byte b,
 // decode writes erased block e from byte e.
@@ -520,9 +552,14 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
   for (int h = 0; h < NQ; ++h) {
     uint32_t o[4][W];
 #pragma unroll
-    for (int w = 0; w < W; ++w)
-      transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
-                 o[1][w], o[2][w], o[3][w]);
+    for (int w = 0; w < W; ++w) {
+      if constexpr (M == 4 && MODE != kDecode)   // state still rotated by g
+        transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
+                   o[1][w], o[2][w], o[3][w], t.tout[0], t.tout[1]);
+      else
+        transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
+                   o[1][w], o[2][w], o[3][w]);
+    }
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
       const int b = 4 * h + bb;
@@ -555,6 +592,14 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
     const uint32_t idx = r * lanes + lane;
     return idx < n ? c0 + idx * NC : c0;
   };
+  // Leading window positions of the first group with no block above any
+  // present one: their LFSR steps are skipped (see absorb_item).
+  int lead = 0;
+#pragma unroll
+  for (int q = 0; q < M - 1; ++q) {
+    const int j = src.k_pad() - 1 - q;
+    if (lead == q && (j >= src.k() || src.data(j) == nullptr)) lead = q + 1;
+  }
 
   uint32_t s[4 * W][M / 4];
   uint32_t a[M][W], b[M][W];
@@ -579,7 +624,7 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
     // past the last item the prefetch is a dummy (and is unused)
     load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, !more,
                                     nxt);
-    absorb_item<M, W, MODE>(s, cur, g < groups, lds, t);
+    absorb_item<M, W, MODE>(s, cur, g < groups, g == 0 ? lead : 0, lds, t);
     if (g == groups - 1) unrotate<M, W, MODE>(s, t);
     if (g == items - 1) {
       finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, t);
