@@ -194,7 +194,16 @@ typedef struct rs_poly_launch {
                            * calls with few columns use smaller tiles so that  *
                            * every workgroup gets work                         */
     int wgs_per_cu;       /* persistent workgroups per CU: 1 or 2              */
+    int table_placement;  /* LFSR tables in LDS: RS_POLY_TABLES_PACKED or      *
+                           * RS_POLY_TABLES_NIBBLE                             */
 } rs_poly_launch_t;
+
+/* Table placements of the LFSR feedback products T[f] (both give identical
+ * results).  PACKED: one 256-entry table per rotation, one LDS lookup per
+ * symbol.  NIBBLE: split-nibble tables, T[f] = T[f & 15] ^ T[f & 0xF0]
+ * from two 16-entry tables, two lookups per symbol and 1/8 of the LDS. */
+#define RS_POLY_TABLES_PACKED 0
+#define RS_POLY_TABLES_NIBBLE 1
 
 #define RS_POLY_OP_ENCODE 0
 #define RS_POLY_OP_DECODE 1
@@ -252,7 +261,8 @@ int rs_poly_batch_get_launch(const rs_poly_batch_t *b, int op, int wide,
 int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide,
                              const rs_poly_launch_t *cfg);
 
-/* Autotuner: times every candidate launch shape on these stripes (running
+/* Autotuner: times every candidate launch shape (bytes per lane, threads,
+ * tile, workgroups per CU, table placement) on these stripes (running
  * the real operation several times on `stream`: encode and decode are
  * idempotent, and an update runs an even number of times per candidate, so
  * the parity ends as it began -- tuning does not apply the update),

@@ -139,7 +139,8 @@ class Stripe(ctypes.Structure):
 class Launch(ctypes.Structure):
     """rs_poly_launch_t."""
     _fields_ = [("bytes_per_lane", ctypes.c_int), ("threads", ctypes.c_int),
-                ("tile_bytes", ctypes.c_int), ("wgs_per_cu", ctypes.c_int)]
+                ("tile_bytes", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
+                ("table_placement", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -148,6 +149,8 @@ class Launch(ctypes.Structure):
 RS_POLY_OP_ENCODE = 0
 RS_POLY_OP_DECODE = 1
 RS_POLY_OP_UPDATE = 2
+RS_POLY_TABLES_PACKED = 0
+RS_POLY_TABLES_NIBBLE = 1
 
 
 def check(rc, where):

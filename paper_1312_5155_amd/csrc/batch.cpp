@@ -37,7 +37,7 @@ struct GroupBuf {
   uint64_t version = 0;           // bumped when device buffers move
 };
 
-using GraphKey = std::tuple<int, int, int, int, int, uint64_t>;
+using GraphKey = std::tuple<int, int, int, int, int, int, uint64_t>;
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
@@ -50,6 +50,8 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
   const Mode mode = op == RS_POLY_OP_DECODE ? kDecode : op == RS_POLY_OP_UPDATE ? kUpdate : kEncode;
   if (c.threads > codec_max_threads(mode, wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
   if (c.tile_bytes < 4096 || c.tile_bytes % 16 != 0) return false;
+  if (c.table_placement != RS_POLY_TABLES_PACKED && c.table_placement != RS_POLY_TABLES_NIBBLE)
+    return false;
   return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 2;
 }
 
@@ -73,6 +75,7 @@ rs_poly_launch_t default_launch(int op, int wide) {
   }
   // (a wide decode workgroup takes 128 KiB of LDS: one fits per CU)
   c.wgs_per_cu = op == RS_POLY_OP_DECODE && wide ? 1 : 2;
+  c.table_placement = RS_POLY_TABLES_PACKED;
   return c;
 }
 
@@ -196,7 +199,8 @@ int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
 int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
                              hipGraphExec_t *out) {
   GroupBuf &gb = groups[wide];
-  const GraphKey key{op, wide, cfg.bytes_per_lane, cfg.threads, cfg.wgs_per_cu, gb.version};
+  const GraphKey key{op,          wide,           cfg.bytes_per_lane, cfg.threads,
+                     cfg.wgs_per_cu, cfg.table_placement, gb.version};
   auto it = graphs.find(key);
   if (it != graphs.end()) {
     *out = it->second.exec;
@@ -210,6 +214,7 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
   lc.threads = cfg.threads;
   lc.grid = num_cu * cfg.wgs_per_cu;
   lc.bytewise = false;
+  lc.nibble = cfg.table_placement == RS_POLY_TABLES_NIBBLE;
   GraphEntry e;
   if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return RS_EDEVICE;
@@ -480,8 +485,8 @@ bool cache_lookup(const char *path, const std::string &key, rs_poly_launch_t *ou
     rs_poly_launch_t c;
     const char *p = strstr(line, "\"bytes_per_lane\":");
     if (!p || sscanf(p, "\"bytes_per_lane\": %d, \"threads\": %d, \"tile_bytes\": %d, "
-                        "\"wgs_per_cu\": %d", &c.bytes_per_lane, &c.threads, &c.tile_bytes,
-                     &c.wgs_per_cu) != 4)
+                        "\"wgs_per_cu\": %d, \"table_placement\": %d", &c.bytes_per_lane,
+                     &c.threads, &c.tile_bytes, &c.wgs_per_cu, &c.table_placement) != 5)
       continue;
     *out = c;
     found = true;  // the last matching line wins
@@ -496,8 +501,9 @@ void cache_store(const char *path, const std::string &key, const rs_poly_launch_
   if (!f) return;
   fprintf(f,
           "{%s, \"bytes_per_lane\": %d, \"threads\": %d, \"tile_bytes\": %d, "
-          "\"wgs_per_cu\": %d, \"ms\": %.4f}\n",
-          key.c_str(), c.bytes_per_lane, c.threads, c.tile_bytes, c.wgs_per_cu, ms);
+          "\"wgs_per_cu\": %d, \"table_placement\": %d, \"ms\": %.4f}\n",
+          key.c_str(), c.bytes_per_lane, c.threads, c.tile_bytes, c.wgs_per_cu,
+          c.table_placement, ms);
   fclose(f);
 }
 
@@ -629,36 +635,37 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
     }
     rs_poly_launch_t winner = b->launch[op][w];
     double winner_ms = 1e30;
-    const int bpls[] = {4, 8, 16};
-    const int threads[] = {256, 512, 1024};
-    const int tiles[] = {16 << 10, 64 << 10, 256 << 10};
-    for (int bpl : bpls)
-      for (int th : threads)
-        for (int tile : tiles)
-          for (int wgs = 1; wgs <= 2; ++wgs) {
-            const rs_poly_launch_t c{bpl, th, tile, wgs};
-            if (!valid_launch(op, w, c)) continue;
-            b->launch[op][w] = c;
-            // one warm-up (also captures the graph), then 3 timed runs: an
-            // even count, so an update leaves the parity as it found it
-            double ms = 0;
-            for (int rep = 0; rep < 4 && status == RS_OK; ++rep) {
-              if (rep == 1) (void)hipEventRecord(e0, st);
-              status = b->run(op, sub[w].data(), (int)sub[w].size(), stream);
+    // every valid launch shape and table placement
+    std::vector<rs_poly_launch_t> cands;
+    for (int bpl : {4, 8, 16})
+      for (int th : {256, 512, 1024})
+        for (int tile : {16 << 10, 64 << 10, 256 << 10})
+          for (int wgs = 1; wgs <= 2; ++wgs)
+            for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE}) {
+              const rs_poly_launch_t c{bpl, th, tile, wgs, tp};
+              if (valid_launch(op, w, c)) cands.push_back(c);
             }
-            if (status != RS_OK) break;
-            (void)hipEventRecord(e1, st);
-            float f = 0;
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess) {
-              status = RS_EDEVICE;
-              break;
-            }
-            ms = f / 3.0;
-            if (ms < winner_ms) {
-              winner_ms = ms;
-              winner = c;
-            }
-          }
+    for (const rs_poly_launch_t &c : cands) {
+      b->launch[op][w] = c;
+      // one warm-up (also captures the graph), then 3 timed runs: an even
+      // count, so an update leaves the parity as it found it
+      for (int rep = 0; rep < 4 && status == RS_OK; ++rep) {
+        if (rep == 1) (void)hipEventRecord(e0, st);
+        status = b->run(op, sub[w].data(), (int)sub[w].size(), stream);
+      }
+      if (status != RS_OK) break;
+      (void)hipEventRecord(e1, st);
+      float f = 0;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess) {
+        status = RS_EDEVICE;
+        break;
+      }
+      const double ms = f / 3.0;
+      if (ms < winner_ms) {
+        winner_ms = ms;
+        winner = c;
+      }
+    }
     b->launch[op][w] = winner;
     if (cache && status == RS_OK) cache_store(cache, key, winner, winner_ms);
   }

@@ -57,6 +57,12 @@
 namespace rsp {
 namespace {
 
+// A kernel variant (the MODE template argument below): the operation in the
+// low two bits, the LFSR table placement in the next one.
+constexpr int kNibbleBit = 4;
+constexpr int op_of(int v) { return v & 3; }
+constexpr bool nibble_of(int v) { return (v & kNibbleBit) != 0; }
+
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
   return __builtin_amdgcn_perm(hi, lo, sel);
 }
@@ -126,18 +132,27 @@ __device__ __forceinline__ void st4(uint8_t *lds, uint32_t off, uint32_t a, uint
 // per remainder byte) in bytes 128..255.  Decode of m > 4 (8-byte entries)
 // needs whole rows for both, so its apply tables sit in a second 64 KiB
 // region (128 KiB of LDS, one workgroup per CU).
+//
+// Split-nibble placement (the alternative the autotuner can pick): each
+// rotated copy of T' is two 16-entry tables, T'[n] in rows 0..15 and
+// T'[n << 4] in rows 16..31 (T' is GF(2)-linear, so T'[f] is their XOR).  A
+// step then makes two lookups instead of one; encode and update need 8 KiB
+// of LDS instead of 64.
 template <int M, int MODE>
 struct Layout {
-  static constexpr bool kTwoRegions = M == 8 && MODE == kDecode;
+  static constexpr bool kNibble = nibble_of(MODE);
+  static constexpr uint32_t kHiBase = 16 * kRowBytes;   // nibble: rows of T'[n << 4]
+  static constexpr bool kTwoRegions = M == 8 && op_of(MODE) == kDecode;
   static constexpr uint32_t kEntry = M == 4 ? 4 : 8;              // bytes per value
   static constexpr uint32_t kCopies = M;                          // rotations 1..M bytes
   static constexpr uint32_t kLfsrReps =
-      (MODE == kDecode && !kTwoRegions ? 128 : 256) / (kCopies * kEntry);
+      (op_of(MODE) == kDecode && !kTwoRegions ? 128 : 256) / (kCopies * kEntry);
   static constexpr uint32_t kCopyBytes = kLfsrReps * kEntry;      // one rotated copy
   static constexpr uint32_t kApplyReps = (kTwoRegions ? 256 : 128) / (M * kEntry);
   static constexpr uint32_t kTableBytes = kApplyReps * kEntry;    // one apply table
   static constexpr uint32_t kApplyBase = kTwoRegions ? 65536 : 128;
-  static constexpr uint32_t kLdsBytes = kTwoRegions ? 131072 : 65536;
+  static constexpr uint32_t kLdsBytes =
+      kTwoRegions ? 131072 : kNibble && op_of(MODE) != kDecode ? 32 * kRowBytes : 65536;
   // Lane groups at different rotation phases: in one LDS read group g uses
   // copy (q + g) mod M, so the 32 lanes of a pass cover 32 distinct
   // replica slots (banks).
@@ -162,6 +177,7 @@ struct Layout {
 template <int M, int MODE>
 struct Lanes {
   uint32_t lsel[M], loff[M];   // LFSR step q: v_perm selector, byte offset
+  uint32_t loffhi[M];          // split-nibble: offset of the high-nibble table
   uint32_t tin[2], tout[2];    // M = 4: rotating transpose selectors (in, out)
   uint32_t rin[2], rout[2];    // M = 8: v_perm selectors (low, high dword)
   uint32_t asel[M], aoff[M];   // decode apply, slot b
@@ -181,6 +197,7 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
     // <- byte p of the dword pair (selector p: 0..3 low dword, 4..7 high).
     t.lsel[q] = M == 4 ? 0x0C0C0400u | (p << 8) : 0x0C0C000Cu | (p << 8);
     t.loff[q] = p * L::kCopyBytes + rep * L::kEntry;
+    t.loffhi[q] = L::kHiBase + t.loff[q];
   }
   t.tin[0] = rotl32(kT2a, 8 * g);
   t.tin[1] = rotl32(kT2b, 8 * g);
@@ -200,7 +217,7 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
     t.rout[0] |= ((i + g) & 7) << (8 * i);
     t.rout[1] |= ((i + 4 + g) & 7) << (8 * i);
   }
-  if constexpr (MODE == kDecode) {
+  if constexpr (op_of(MODE) == kDecode) {
     const uint32_t arep = lane & (L::kApplyReps - 1);
     const uint32_t ga = (lane / L::kApplyReps) % M;
 #pragma unroll
@@ -214,13 +231,16 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
   return t;
 }
 
-// Expands the LFSR tables: copy v (0..M-1) of entry f is rotl(T'[f], 8(v+1)).
+// Expands the LFSR tables: copy v (0..M-1) of entry f is rotl(T'[f], 8(v+1));
+// split-nibble: row r < 16 holds entry r, row 16 + r entry r << 4.
 template <int M, int MODE>
 __device__ void build_lfsr_tables(uint8_t *lds, const uint32_t *basis) {
   using L = Layout<M, MODE>;
-  for (uint32_t idx = threadIdx.x; idx < 256 * L::kCopies; idx += blockDim.x) {
-    const uint32_t f = idx / L::kCopies, v = idx % L::kCopies;
-    const uint32_t base = f * kRowBytes + v * L::kCopyBytes;
+  constexpr uint32_t kRows = L::kNibble ? 32 : 256;
+  for (uint32_t idx = threadIdx.x; idx < kRows * L::kCopies; idx += blockDim.x) {
+    const uint32_t r = idx / L::kCopies, v = idx % L::kCopies;
+    const uint32_t f = !L::kNibble ? r : r < 16 ? r : (r - 16) << 4;
+    const uint32_t base = r * kRowBytes + v * L::kCopyBytes;
     uint32_t lo, hi;
     if constexpr (M == 4) {
       lo = hi = rotl32(lin32(f, basis), 8 * (v + 1));
@@ -334,7 +354,30 @@ __device__ __forceinline__ void store_cols(uint8_t *ptr, uint32_t col, uint32_t 
 template <int M, int MODE>
 __device__ __forceinline__ void lfsr_step(uint32_t (&s)[M / 4], const uint8_t *lds,
                                           const Lanes<M, MODE> &t, int q) {
-  if constexpr (M == 4) {
+  if constexpr (Layout<M, MODE>::kNibble) {
+    // x = f << 8 (| the lane offset for M = 4); two lookups, rows f & 15
+    // and 16 + (f >> 4)
+    uint32_t lo, hi;
+    if constexpr (M == 4) {
+      const uint32_t x = perm(s[0], t.loff[q], t.lsel[q]);
+      lo = x & 0xFFFu;
+      hi = (x >> 4) & 0xF00u;
+    } else {
+      const uint32_t x = perm(s[1], s[0], t.lsel[q]);
+      lo = (x & 0xF00u) | t.loff[q];
+      hi = (x >> 4) & 0xF00u;
+    }
+    hi |= t.loffhi[q];
+    if constexpr (M == 4) {
+      s[0] ^= *reinterpret_cast<const uint32_t *>(lds + lo) ^
+              *reinterpret_cast<const uint32_t *>(lds + hi);
+    } else {
+      const uint2 a = *reinterpret_cast<const uint2 *>(lds + lo);
+      const uint2 b = *reinterpret_cast<const uint2 *>(lds + hi);
+      s[0] ^= a.x ^ b.x;
+      s[1] ^= a.y ^ b.y;
+    }
+  } else if constexpr (M == 4) {
     const uint32_t addr = perm(s[0], t.loff[q], t.lsel[q]);
     s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
   } else {
@@ -424,7 +467,7 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
     const uint8_t *ptr;
     if (dummy) {
       ptr = nullptr;
-    } else if (MODE != kEncode && g == groups) {
+    } else if (op_of(MODE) != kEncode && g == groups) {
       const int i = src.m() - 1 - q;
       ptr = i >= 0 ? src.par_in(i) : nullptr;
     } else {
@@ -524,7 +567,7 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
   constexpr int NQ = M / 4;
   constexpr int NC = 4 * W;
   const int m = src.m(), n_out = src.n_out();
-  if constexpr (MODE == kDecode) {
+  if constexpr (op_of(MODE) == kDecode) {
     // Column by column (few live registers): every lane walks all M tables
     // (those past m are zero) in its rotated order.
 #pragma unroll
@@ -553,7 +596,7 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
     uint32_t o[4][W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      if constexpr (M == 4 && MODE != kDecode)   // state still rotated by g
+      if constexpr (M == 4 && op_of(MODE) != kDecode)   // state still rotated by g
         transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
                    o[1][w], o[2][w], o[3][w], t.tout[0], t.tout[1]);
       else
@@ -563,7 +606,7 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
       const int b = 4 * h + bb;
-      const int oi = MODE == kDecode ? b : m - 1 - b;
+      const int oi = op_of(MODE) == kDecode ? b : m - 1 - b;
       if (oi >= 0 && oi < n_out && active)
         store_cols<W, BYTEWISE>(src.out(oi), col, src.B(), o[bb]);
     }
@@ -586,7 +629,7 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
   constexpr uint32_t NC = 4 * W;
   if (n == 0) return;
   const int groups = src.k_pad() / M;
-  const int items = groups + (MODE == kEncode ? 0 : 1);
+  const int items = groups + (op_of(MODE) == kEncode ? 0 : 1);
   const uint32_t rounds = (n + lanes - 1) / lanes;
   auto col_of = [&](uint32_t r) {
     const uint32_t idx = r * lanes + lane;
@@ -664,7 +707,7 @@ __device__ __forceinline__ void process_range(const Src &src, uint32_t c0, uint3
 // 8 apply tables).  The wide decode has no 16-byte variant.
 template <int M, int W, int MODE>
 constexpr int max_threads() {
-  if (M == 8 && MODE == kDecode) return W == 4 ? 0 : W == 2 ? 512 : 1024;
+  if (M == 8 && op_of(MODE) == kDecode) return W == 4 ? 0 : W == 2 ? 512 : 1024;
   return W == 4 ? (M == 8 ? 256 : 512) : 1024;
 }
 
@@ -674,7 +717,7 @@ __global__ void __launch_bounds__((max_threads<M, W, MODE>()))
 __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) codec_kernel(CodecParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[Layout<M, MODE>::kLdsBytes];
   build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
-  if constexpr (MODE == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
+  if constexpr (op_of(MODE) == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
   __syncthreads();
 
   constexpr uint32_t NC = 4 * W;
@@ -750,7 +793,7 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
     const uint32_t s = tile_stripe[tile];
     const StripeDesc d = load_desc(descs + s);
     const bool new_lfsr = d.lfsr_set != staged_lfsr;
-    const bool new_apply = MODE == kDecode && d.apply_set != staged_apply;
+    const bool new_apply = op_of(MODE) == kDecode && d.apply_set != staged_apply;
     if (new_lfsr || new_apply) {
       // The barrier at the end of the previous tile guarantees no wave still
       // reads the old tables.
@@ -794,7 +837,7 @@ BatchFn pick_batch(int sb, int w) {
     if (w == 2) return batch_kernel<4, 2, MODE>;
     return batch_kernel<4, 1, MODE>;
   }
-  if constexpr (MODE != kDecode) {
+  if constexpr (op_of(MODE) != kDecode) {
     if (w == 4) return batch_kernel<8, 4, MODE>;
   }
   if (w >= 2) return batch_kernel<8, 2, MODE>;
@@ -832,9 +875,16 @@ int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
                      0, st, g);
   int err = (int)hipGetLastError();
   if (err) return err;
-  BatchFn fn = mode == kEncode   ? pick_batch<kEncode>(sb, cfg.dwords_per_lane)
-               : mode == kDecode ? pick_batch<kDecode>(sb, cfg.dwords_per_lane)
-                                 : pick_batch<kUpdate>(sb, cfg.dwords_per_lane);
+  const int w = cfg.dwords_per_lane;
+  BatchFn fn;
+  switch ((int)mode | (cfg.nibble ? kNibbleBit : 0)) {
+    case kEncode: fn = pick_batch<kEncode>(sb, w); break;
+    case kDecode: fn = pick_batch<kDecode>(sb, w); break;
+    case kUpdate: fn = pick_batch<kUpdate>(sb, w); break;
+    case kEncode | kNibbleBit: fn = pick_batch<kEncode | kNibbleBit>(sb, w); break;
+    case kDecode | kNibbleBit: fn = pick_batch<kDecode | kNibbleBit>(sb, w); break;
+    default: fn = pick_batch<kUpdate | kNibbleBit>(sb, w); break;
+  }
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0, st, g);
   return (int)hipGetLastError();
 }

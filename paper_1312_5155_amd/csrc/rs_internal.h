@@ -61,6 +61,7 @@ struct LaunchCfg {
   int threads;           // workgroup size, multiple of 64, <= 1024
   int grid;              // workgroups; 0 = pick from the size
   bool bytewise;         // byte loads/stores (for misaligned blocks)
+  bool nibble;           // batch kernels: split-nibble LFSR tables
 };
 
 // Launches the codec kernel for one stripe.  Returns a hipError_t as int.

@@ -203,6 +203,20 @@ def test_batch_update_mixed_matches_oracle():
         c.check()
 
 
+@pytest.mark.parametrize("placement", [B.RS_POLY_TABLES_PACKED, B.RS_POLY_TABLES_NIBBLE])
+def test_batch_update_table_placements(placement):
+    say(f"batch update placement={placement}")
+    cases = batch_cases(65, 16, ((10, 4), (32, 8), (6, 3)), 1, 200000)
+    bt = B.Batch()
+    for wide in (0, 1):
+        cfg = bt.get_launch(B.RS_POLY_OP_UPDATE, wide).as_dict()
+        bt.set_launch(B.RS_POLY_OP_UPDATE, wide, dict(cfg, table_placement=placement))
+    bt.update(entries(cases))
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check()
+
+
 def test_batch_update_equals_plain_update():
     say("batch update vs plain")
     cases = batch_cases(62, 12, ((10, 4), (32, 8)), 4096, 1 << 20)
