@@ -39,9 +39,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, src_hash):
+def measured_traffic(kernel, src_hash, variant):
     """HBM bytes per launch from the committed counter summary, or None if
-    it is missing or was taken on other kernel sources."""
+    it is missing, was taken on other kernel sources, or on another kernel
+    variant than the one this run launched."""
     path = os.path.join(ROOT, "profiles", "traffic_rs104_256x1MiB.json")
     try:
         with open(path) as fh:
@@ -50,7 +51,22 @@ def measured_traffic(kernel, src_hash):
         return None
     if rec.get("kernel_source_hash") != src_hash:
         return None
-    return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    entry = rec.get("kernels", {}).get(kernel, {})
+    if entry.get("kernel") != variant:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def batch_variant(op, launch, m=4, matrix_update=False):
+    """Name of the batch kernel template a launch shape runs (state width 4
+    for m <= 4), as the profiler prints it.  An update of at most 8 changed
+    blocks per stripe runs the generator-matrix form (mode 3), which has no
+    table-placement variants."""
+    if op == 2 and matrix_update:
+        mode = 3
+    else:
+        mode = op + (4 if launch["table_placement"] else 0)
+    return f"batch_kernel<{4 if m <= 4 else 8}, {launch['bytes_per_lane'] // 4}, {mode}>"
 
 
 CALIB_BYTES = 1 << 30       # size of the copy that calibrates the counters
@@ -105,15 +121,11 @@ def traffic_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path
     fetch = _counter_means(fetch_csv, "FETCH_SIZE")
     write = _counter_means(write_csv, "WRITE_SIZE")
     kernels = {}
-    for label, key in (("batch_encode", "batch_kernel<4, 4, 0>"),
-                       ("batch_encode", "batch_kernel<4, 2, 0>"),
-                       ("batch_encode", "batch_kernel<4, 1, 0>"),
-                       ("batch_decode", "batch_kernel<4, 4, 1>"),
-                       ("batch_decode", "batch_kernel<4, 2, 1>"),
-                       ("batch_decode", "batch_kernel<4, 1, 1>"),
-                       ("batch_update", "batch_kernel<4, 4, 2>"),
-                       ("batch_update", "batch_kernel<4, 2, 2>"),
-                       ("batch_update", "batch_kernel<4, 1, 2>")):
+    variants = [(label, f"batch_kernel<4, {w}, {op + tp}>")
+                for label, op in (("batch_encode", 0), ("batch_decode", 1), ("batch_update", 2),
+                                  ("batch_update", 3))
+                for w in (4, 2, 1) for tp in ((0, 4) if op < 3 else (0,))]
+    for label, key in variants:
         fv = [v for n, (v, c) in fetch.items() if key in n]
         wv = [v for n, (v, c) in write.items() if key in n]
         if not fv or not wv:
@@ -532,11 +544,16 @@ def main():
     }
     if update:
         kernels["batch_update"] = update
+    ops = {"batch_encode": B.RS_POLY_OP_ENCODE, "batch_decode": B.RS_POLY_OP_DECODE,
+           "batch_update": B.RS_POLY_OP_UPDATE}
     for label in kernels:
-        kernels[label]["traffic"] = measured_traffic(label, src_hash)
+        variant = batch_variant(ops[label], batch.get_launch(ops[label], 0).as_dict(),
+                                matrix_update=True)   # one changed block per stripe
+        kernels[label]["kernel"] = variant
+        kernels[label]["traffic"] = measured_traffic(label, src_hash, variant)
     dom = "batch_encode" if enc_ms >= dec_ms else "batch_decode"
     achieved = kernels[dom]["gbs"]
-    traffic = measured_traffic(dom, src_hash)
+    traffic = kernels[dom]["traffic"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
@@ -574,7 +591,8 @@ def main():
         "hbm_frac": round((enc_alg + dec_alg) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": kernels,
         "launch": {"encode": batch.get_launch(B.RS_POLY_OP_ENCODE, 0).as_dict(),
-                   "decode": batch.get_launch(B.RS_POLY_OP_DECODE, 0).as_dict()},
+                   "decode": batch.get_launch(B.RS_POLY_OP_DECODE, 0).as_dict(),
+                   "update": batch.get_launch(B.RS_POLY_OP_UPDATE, 0).as_dict()},
         "plain": plain,
         "serving": serve,
         "roofline": roofline,

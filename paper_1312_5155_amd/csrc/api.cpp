@@ -116,6 +116,34 @@ int update_span(const Code &c, const uint8_t *const *delta) {
   return span;
 }
 
+int update_changed(const Code &c, const uint8_t *const *delta, int *which) {
+  int n = 0;
+  for (int j = 0; j < c.k(); ++j)
+    if (delta[j]) {
+      if (n < kMatrixMaxBlocks) which[n] = j;
+      ++n;
+    }
+  return n;
+}
+
+void fill_matrix_update_params(const Code &c, const uint8_t *const *delta,
+                               uint8_t *const *parity, const int *which, int n,
+                               uint64_t offset, uint64_t B, CodecParams *p) {
+  for (int t = 0; t < n; ++t) {
+    p->data[t] = delta[which[t]] + offset;
+    c.column_basis(which[t], p->apply_basis[t]);
+  }
+  for (int i = 0; i < c.m(); ++i) {
+    p->par_in[i] = parity[i] + offset;
+    p->out[i] = parity[i] + offset;
+  }
+  p->block_bytes = B;
+  p->k = n;
+  p->m = c.m();
+  p->k_pad = round_up(n, c.state_bytes());
+  p->n_out = c.m();
+}
+
 void fill_update_params(const Code &c, const uint8_t *const *delta, uint8_t *const *parity,
                         int span, uint64_t offset, uint64_t B, CodecParams *p) {
   for (int j = 0; j < span; ++j) p->data[j] = delta[j] ? delta[j] + offset : nullptr;
@@ -240,6 +268,11 @@ int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta, uint8_t *const *pa
   // starts there.  No changed block at all leaves the parity as it is.
   const int span = update_span(c, delta);
   if (block_bytes == 0 || span == 0) return RS_OK;
+  // Up to kMatrixMaxBlocks changed blocks: the generator-matrix form, one
+  // lookup per changed block (Sec. 6); more: the LFSR form.
+  int which[kMatrixMaxBlocks];
+  const int changed = update_changed(c, delta, which);
+  const Mode mode = changed <= kMatrixMaxBlocks ? kUpdateMatrix : kUpdate;
 
   std::lock_guard<std::mutex> lock(h->mu);
   const int ncu = device_cu_count();
@@ -250,10 +283,13 @@ int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta, uint8_t *const *pa
     const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
     CodecParams p;
     memset(&p, 0, sizeof(p));
-    fill_update_params(c, delta, parity, span, off, piece, &p);
+    if (mode == kUpdateMatrix)
+      fill_matrix_update_params(c, delta, parity, which, changed, off, piece, &p);
+    else
+      fill_update_params(c, delta, parity, span, off, piece, &p);
     p.zero_page = zp;
-    const LaunchCfg cfg = default_cfg(kUpdate, sb, piece, align, ncu);
-    const int rc = hip_status(launch_codec(kUpdate, sb, p, cfg, stream));
+    const LaunchCfg cfg = default_cfg(mode, sb, piece, align, ncu);
+    const int rc = hip_status(launch_codec(mode, sb, p, cfg, stream));
     if (rc != RS_OK) return rc;
   }
   return RS_OK;

@@ -24,6 +24,9 @@ namespace rsp {
 namespace {
 
 constexpr int kOps = 3;     // encode, decode, update
+// Graph key of a batched update in the generator-matrix form (same launch
+// shape as RS_POLY_OP_UPDATE).
+constexpr int kOpUpdateMatrix = 3;
 constexpr int kWidths = 2;  // state width 4 bytes (m <= 4), 8 bytes (m <= 8)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -59,11 +62,7 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
 // RS(32,8) for wide codes), MI355X; the autotuner refines them per workload.
 rs_poly_launch_t default_launch(int op, int wide) {
   rs_poly_launch_t c;
-  if (op != RS_POLY_OP_DECODE && !wide) {
-    c.bytes_per_lane = 8;
-    c.threads = 1024;
-    c.tile_bytes = 16 << 10;
-  } else if (wide) {
+  if (wide) {
     // RS(32,8), 64 x 32 x 4 MiB stripes
     c.bytes_per_lane = op == RS_POLY_OP_DECODE ? 4 : 8;
     c.threads = 1024;
@@ -74,7 +73,7 @@ rs_poly_launch_t default_launch(int op, int wide) {
     c.tile_bytes = 16 << 10;
   }
   // (a wide decode workgroup takes 128 KiB of LDS: one fits per CU)
-  c.wgs_per_cu = op == RS_POLY_OP_DECODE && wide ? 1 : 2;
+  c.wgs_per_cu = wide ? (op == RS_POLY_OP_DECODE ? 1 : 2) : (op == RS_POLY_OP_DECODE ? 2 : 1);
   c.table_placement = RS_POLY_TABLES_PACKED;
   return c;
 }
@@ -220,6 +219,7 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
     return RS_EDEVICE;
   const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
                     : op == RS_POLY_OP_UPDATE ? kUpdate
+                    : op == kOpUpdateMatrix   ? kUpdateMatrix
                                               : kEncode;
   const int lerr = launch_batch(mode, wide ? 8 : 4, g, gb.tile_cap, lc, capture);
   const hipError_t cerr = hipStreamEndCapture(capture, &e.graph);
@@ -247,6 +247,9 @@ struct GroupPlan {
   std::vector<uint32_t> apply;  // kMaxM*16 per set
   std::unordered_map<const Code *, uint32_t> lfsr_index;
   std::unordered_map<const DecodePlan *, uint32_t> apply_index;
+  // matrix-form update: table bases per (code, changed-block set)
+  std::map<std::pair<const Code *, std::vector<int>>, uint32_t> matrix_index;
+  bool matrix = false;   // update group in the generator-matrix form
   std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
   uint64_t tiles = 0;
   uint32_t tile_cols = 0;
@@ -309,6 +312,18 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   if (count < 0) return RS_EINVAL;
   if (count > 0 && !stripes) return RS_ENULL;
   GroupPlan plan[kWidths];
+  // Updates: a state width's stripes take the generator-matrix form when
+  // none of them changes more than kMatrixMaxBlocks blocks.
+  if (op == RS_POLY_OP_UPDATE) {
+    plan[0].matrix = plan[1].matrix = true;
+    for (int i = 0; i < count; ++i) {
+      const rs_poly_stripe_t &st = stripes[i];
+      if (!st.code || !st.blocks) continue;   // rejected below
+      int which[kMatrixMaxBlocks];
+      if (update_changed(st.code->code, st.blocks, which) > kMatrixMaxBlocks)
+        plan[st.code->code.state_bytes() == 8].matrix = false;
+    }
+  }
 
   // Validate everything first; build the per-group host layout.
   for (int i = 0; i < count; ++i) {
@@ -333,6 +348,19 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     }
     lset = li->second;
     uint32_t aset = 0;
+    int which[kMatrixMaxBlocks];
+    const int changed = op == RS_POLY_OP_UPDATE ? update_changed(c, st.blocks, which) : 0;
+    if (gp.matrix) {
+      std::pair<const Code *, std::vector<int>> key{&c, std::vector<int>(which, which + changed)};
+      auto mi = gp.matrix_index.find(key);
+      if (mi == gp.matrix_index.end()) {
+        mi = gp.matrix_index.emplace(key, (uint32_t)(gp.apply.size() / (kMaxM * 16))).first;
+        uint32_t bases[kMaxM][16] = {};
+        for (int t = 0; t < changed; ++t) c.column_basis(which[t], bases[t]);
+        gp.apply.insert(gp.apply.end(), &bases[0][0], &bases[0][0] + kMaxM * 16);
+      }
+      aset = mi->second;
+    }
     if (op == RS_POLY_OP_DECODE) {
       auto ai = gp.apply_index.find(dp.get());
       if (ai == gp.apply_index.end()) {
@@ -348,10 +376,12 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     for (uint64_t off = 0; off < st.block_bytes; off += kMaxPieceBytes) {
       StripeDesc d{};
       d.block_bytes = std::min<uint64_t>(kMaxPieceBytes, st.block_bytes - off);
-      // update: the LFSR starts at the highest changed block
-      d.k = span;
+      // update: the LFSR starts at the highest changed block; the matrix
+      // form reads the changed blocks only
+      const int kk = gp.matrix ? changed : span;
+      d.k = kk;
       d.m = m;
-      d.k_pad = (span + c.state_bytes() - 1) / c.state_bytes() * c.state_bytes();
+      d.k_pad = (kk + c.state_bytes() - 1) / c.state_bytes() * c.state_bytes();
       d.ptr_off = gp.ptrs.size();
       d.lfsr_set = lset;
       d.apply_set = aset;
@@ -363,7 +393,10 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
         for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
       } else if (op == RS_POLY_OP_UPDATE) {
         d.n_out = m;
-        for (int j = 0; j < span; ++j) gp.ptrs.push_back(st.blocks[j] ? at(j) : 0);
+        if (gp.matrix)
+          for (int t = 0; t < changed; ++t) gp.ptrs.push_back(at(which[t]));
+        else
+          for (int j = 0; j < span; ++j) gp.ptrs.push_back(st.blocks[j] ? at(j) : 0);
         for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
         for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
       } else {
@@ -454,7 +487,7 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   for (int w = 0; w < kWidths; ++w) {
     if (plan[w].descs.empty()) continue;
     hipGraphExec_t exec;
-    rc = graph_for(op, w, launch[op][w], &exec);
+    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], &exec);
     if (rc != RS_OK) return rc;
     if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
   }

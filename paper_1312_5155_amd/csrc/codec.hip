@@ -37,6 +37,13 @@
 // the old parity is XORed in as decode does, and the result overwrites the
 // parity in place: one read-modify-write pass.
 //
+// Matrix update = the generator-matrix form of Sec. 6 for an update of at
+// most 8 blocks: the parity change is sum_j P[:, j] * delta_j, with column
+// P[:, j] the remainder of x^(m+j) mod g(x).  Each changed block gets a
+// packed 256-entry table (byte x -> the m products P[i][j] x), so a column
+// costs one lookup per changed block, with no serial chain and no work for
+// the unchanged blocks.
+//
 // LDS tables.  Each table is a GF(2)-linear map of one byte, expanded by
 // every workgroup from 8 basis values passed in the kernel arguments.  Entry
 // e of every table sits at byte e*256 plus the table's offset and the
@@ -153,6 +160,12 @@ struct Layout {
   static constexpr uint32_t kApplyBase = kTwoRegions ? 65536 : 128;
   static constexpr uint32_t kLdsBytes =
       kTwoRegions ? 131072 : kNibble && op_of(MODE) != kDecode ? 32 * kRowBytes : 65536;
+  // Matrix update: one table per changed block, a group of M tables per
+  // item (the item's M blocks), kMatReps replicas; 2 groups per row for
+  // M = 4, 1 for M = 8 (8 tables at most).
+  static constexpr uint32_t kMatReps = M == 4 ? 8 : 4;
+  static constexpr uint32_t kMatTableBytes = kMatReps * kEntry;
+  static constexpr uint32_t kMatGroupBytes = M * kMatTableBytes;
   // Lane groups at different rotation phases: in one LDS read group g uses
   // copy (q + g) mod M, so the 32 lanes of a pass cover 32 distinct
   // replica slots (banks).
@@ -217,6 +230,17 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
     t.rout[0] |= ((i + g) & 7) << (8 * i);
     t.rout[1] |= ((i + 4 + g) & 7) << (8 * i);
   }
+  if constexpr (op_of(MODE) == kUpdateMatrix) {
+    // table of block slot tb of the item, read in per-lane rotated order
+    const uint32_t arep = lane & (L::kMatReps - 1);
+    const uint32_t ga = (lane / L::kMatReps) % M;
+#pragma unroll
+    for (uint32_t b = 0; b < (uint32_t)M; ++b) {
+      const uint32_t tb = (b + ga) & (M - 1);
+      t.asel[b] = M == 4 ? 0x0C0C0400u | (tb << 8) : 0x0C0C000Cu | (tb << 8);
+      t.aoff[b] = tb * L::kMatTableBytes + arep * L::kEntry;
+    }
+  }
   if constexpr (op_of(MODE) == kDecode) {
     const uint32_t arep = lane & (L::kApplyReps - 1);
     const uint32_t ga = (lane / L::kApplyReps) % M;
@@ -274,6 +298,34 @@ __device__ void build_apply_tables(uint8_t *lds, const uint32_t *basis /* [kMaxM
     }
 #pragma unroll
     for (uint32_t r = 0; r < L::kTableBytes / 16; ++r) st4(lds, base + 16 * r, lo, hi, lo, hi);
+  }
+}
+
+// Expands the matrix-update tables.  Window position pos (item pos / M,
+// slot pos mod M) holds changed block t = k_pad - 1 - pos, as load_item
+// places it; tables of positions with no block are zero.
+template <int M>
+__device__ void build_matrix_tables(uint8_t *lds, const uint32_t *basis /* [kMaxM][16] */,
+                                    int c, int k_pad) {
+  using L = Layout<M, kUpdateMatrix>;
+  static_assert(kRowBytes / L::kMatGroupBytes * M == kMatrixMaxBlocks, "one row holds all tables");
+  for (uint32_t idx = threadIdx.x; idx < 256 * kMatrixMaxBlocks; idx += blockDim.x) {
+    const uint32_t f = idx / kMatrixMaxBlocks, pos = idx % kMatrixMaxBlocks;
+    const int tt = k_pad - 1 - (int)pos;
+    const bool used = tt >= 0 && tt < c;
+    const uint32_t base =
+        f * kRowBytes + (pos / M) * L::kMatGroupBytes + (pos % M) * L::kMatTableBytes;
+    uint32_t lo, hi;
+    if constexpr (M == 4) {
+      lo = hi = used ? lin32(f, basis + 16 * tt) : 0u;
+    } else {
+      const uint64_t x = used ? lin64(f, basis + 16 * tt) : 0ull;
+      lo = (uint32_t)x;
+      hi = (uint32_t)(x >> 32);
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < L::kMatTableBytes / 16; ++r)
+      st4(lds, base + 16 * r, lo, hi, lo, hi);
   }
 }
 
@@ -489,26 +541,49 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
   }
 }
 
-// XORs an item into the column states (transposed so that each column's M
-// symbols fill its state window, rotated into the lane's phase: for M = 8
-// only LFSR groups, since the state is brought back before the parity item),
-// then, for an LFSR group, runs its M steps.  The first `skip` steps are
-// left out: they are the leading window positions of the first group that
-// hold no block (padding or absent blocks above every present one), where
-// the state is still zero, so the feedback is zero and a step changes
-// nothing.
+// Matrix update: the packed products of one item (the M changed blocks of
+// group gofs / kMatGroupBytes) for one column, whose M symbols are the bytes
+// of d0 (and d1 for M = 8).  The group offset is an immediate of the reads.
+template <int M, int MODE, uint32_t GOFS>
+__device__ __forceinline__ void matrix_lookups(uint32_t d0, uint32_t d1, uint32_t (&acc)[M / 4],
+                                               const uint8_t *lds, const Lanes<M, MODE> &t) {
+#pragma unroll
+  for (int b = 0; b < M; ++b) {
+    if constexpr (M == 4) {
+      const uint32_t addr = perm(d0, t.aoff[b], t.asel[b]);
+      acc[0] ^= *reinterpret_cast<const uint32_t *>(lds + GOFS + addr);
+    } else {
+      const uint32_t addr = perm(d1, d0, t.asel[b]) | t.aoff[b];
+      const uint2 v = *reinterpret_cast<const uint2 *>(lds + GOFS + addr);
+      acc[0] ^= v.x;
+      acc[1] ^= v.y;
+    }
+  }
+}
+
+// XORs item g into the column states.  The item is transposed so that each
+// column's M symbols fill its state window.  An LFSR group is rotated into
+// the lane's phase (for M = 4 every item is, since the state stays rotated;
+// for M = 8 only LFSR groups, since the state is brought back before the
+// parity item), then runs its M steps.  The first `skip` steps are left
+// out: they are the leading window positions of the first group that hold
+// no block (padding or absent blocks above every present one), where the
+// state is still zero, so the feedback is zero and a step changes nothing.
+// A matrix-update item adds its blocks' packed products instead.
 template <int M, int W, int MODE>
 __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
-                                            bool lfsr, int skip, const uint8_t *lds,
+                                            bool data_item, int g, int skip, const uint8_t *lds,
                                             const Lanes<M, MODE> &t) {
   constexpr int NQ = M / 4;
   constexpr int NC = 4 * W;
+  constexpr bool kMatrix = op_of(MODE) == kUpdateMatrix;
+  const bool lfsr = data_item && !kMatrix;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     uint32_t d[NQ][4];
 #pragma unroll
     for (int h = 0; h < NQ; ++h) {
-      if constexpr (M == 4)
+      if constexpr (M == 4 && !kMatrix)
         transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
                    d[h][1], d[h][2], d[h][3], kT1a, kT1b, t.tin[0], t.tin[1]);
       else
@@ -517,7 +592,20 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      if constexpr (M == 8) {
+      if constexpr (kMatrix) {
+        if (data_item) {
+          uint32_t acc[NQ];
+#pragma unroll
+          for (int h = 0; h < NQ; ++h) acc[h] = 0;
+          constexpr uint32_t kG = Layout<M, MODE>::kMatGroupBytes;
+          if (M == 8 || g == 0)
+            matrix_lookups<M, MODE, 0>(d[0][x], d[NQ - 1][x], acc, lds, t);
+          else
+            matrix_lookups<M, MODE, kG>(d[0][x], d[NQ - 1][x], acc, lds, t);
+#pragma unroll
+          for (int h = 0; h < NQ; ++h) d[h][x] = acc[h];
+        }
+      } else if constexpr (M == 8) {
         if (lfsr) {
           const uint32_t lo = perm(d[1][x], d[0][x], t.rin[0]);
           const uint32_t hi = perm(d[1][x], d[0][x], t.rin[1]);
@@ -596,7 +684,8 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
     uint32_t o[4][W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      if constexpr (M == 4 && op_of(MODE) != kDecode)   // state still rotated by g
+      if constexpr (M == 4 && op_of(MODE) != kDecode &&
+                    op_of(MODE) != kUpdateMatrix)   // state still rotated by g
         transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
                    o[1][w], o[2][w], o[3][w], t.tout[0], t.tout[1]);
       else
@@ -667,8 +756,8 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
     // past the last item the prefetch is a dummy (and is unused)
     load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, !more,
                                     nxt);
-    absorb_item<M, W, MODE>(s, cur, g < groups, g == 0 ? lead : 0, lds, t);
-    if (g == groups - 1) unrotate<M, W, MODE>(s, t);
+    absorb_item<M, W, MODE>(s, cur, g < groups, g, g == 0 ? lead : 0, lds, t);
+    if (op_of(MODE) != kUpdateMatrix && g == groups - 1) unrotate<M, W, MODE>(s, t);
     if (g == items - 1) {
       finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, t);
 #pragma unroll
@@ -716,8 +805,12 @@ template <int M, int W, int MODE, bool BYTEWISE>
 __global__ void __launch_bounds__((max_threads<M, W, MODE>()))
 __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) codec_kernel(CodecParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[Layout<M, MODE>::kLdsBytes];
-  build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
-  if constexpr (op_of(MODE) == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
+  if constexpr (op_of(MODE) == kUpdateMatrix) {
+    build_matrix_tables<M>(lds, &p.apply_basis[0][0], p.k, p.k_pad);
+  } else {
+    build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
+    if constexpr (op_of(MODE) == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
+  }
   __syncthreads();
 
   constexpr uint32_t NC = 4 * W;
@@ -758,16 +851,16 @@ __global__ void batch_prepare_kernel(BatchGroup g) {
 }
 
 // Persistent kernel over every tile of a batch group.  Each workgroup takes
-// the next tile from an atomic counter (prefetched one tile ahead), finds its
-// stripe through the tile map, re-expands the LDS tables only when the
-// stripe's code or erasure pattern differs from the one staged, and encodes
-// or decodes the tile's columns.  Every wave leaves the loop once the counter
-// passes the last tile.
+// the next tile from an atomic counter (prefetched one tile ahead), finds
+// its stripe through the tile map, re-expands the LDS tables only when the
+// stripe's code, erasure pattern or changed-block set differs from the one
+// staged, and encodes, decodes or updates the tile's columns.  Every wave
+// leaves the loop once the counter passes the last tile.
 template <int M, int W, int MODE>
 __global__ void __launch_bounds__((max_threads<M, W, MODE>()))
 __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[Layout<M, MODE>::kLdsBytes];
-  __shared__ uint64_t next_tile;
+  __shared__ uint64_t next_claim;
   BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
   const_as<BatchHeader> chdr = as_const(hdr);
   const uint64_t total = chdr->total_tiles;
@@ -781,24 +874,34 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
   const Lanes<M, MODE> lt = make_lanes<M, MODE>();
   uint32_t staged_lfsr = ~0u, staged_apply = ~0u;
 
-  if (threadIdx.x == 0) next_tile = atomicAdd(counter, 1ull);
+  // Tiles are handed out in order, so the workgroups work on neighbouring
+  // tiles at any moment (measured faster than giving each workgroup its own
+  // run of tiles, which would restage its tables less often).
+  if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
   __syncthreads();
   for (;;) {
     const uint64_t tile =
-        (uint64_t)uniform((uint32_t)(next_tile >> 32)) << 32 | uniform((uint32_t)next_tile);
-    __syncthreads();   // every thread has read next_tile
+        (uint64_t)uniform((uint32_t)(next_claim >> 32)) << 32 | uniform((uint32_t)next_claim);
+    __syncthreads();   // every thread has read next_claim
     if (tile >= total) break;
-    if (threadIdx.x == 0) next_tile = atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
 
     const uint32_t s = tile_stripe[tile];
     const StripeDesc d = load_desc(descs + s);
-    const bool new_lfsr = d.lfsr_set != staged_lfsr;
-    const bool new_apply = op_of(MODE) == kDecode && d.apply_set != staged_apply;
+    constexpr bool kMatrix = op_of(MODE) == kUpdateMatrix;
+    const bool new_lfsr = !kMatrix && d.lfsr_set != staged_lfsr;
+    const bool new_apply =
+        (op_of(MODE) == kDecode || kMatrix) && d.apply_set != staged_apply;
     if (new_lfsr || new_apply) {
       // The barrier at the end of the previous tile guarantees no wave still
       // reads the old tables.
       if (new_lfsr) build_lfsr_tables<M, MODE>(lds, lfsr_sets + 16 * d.lfsr_set);
-      if (new_apply) build_apply_tables<M>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.m);
+      if constexpr (kMatrix) {
+        if (new_apply)
+          build_matrix_tables<M>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.k, d.k_pad);
+      } else {
+        if (new_apply) build_apply_tables<M>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.m);
+      }
       staged_lfsr = d.lfsr_set;
       staged_apply = d.apply_set;
       __syncthreads();
@@ -809,7 +912,7 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
     const uint32_t c0 = (uint32_t)(tile - d.tile_begin) * tile_cols;
     const uint32_t c1 = bytes - c0 > tile_cols ? c0 + tile_cols : bytes;
     process_range<M, W, MODE>(src, c0, c1, threadIdx.x, blockDim.x, lds, lt);
-    __syncthreads();   // tables and next_tile are about to change
+    __syncthreads();   // tables and next_claim are about to change
   }
 }
 
@@ -858,9 +961,15 @@ int codec_max_threads(Mode mode, int sb, int dwords_per_lane) {
 }
 
 int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, void *stream) {
-  KernelFn fn = mode == kEncode   ? pick<kEncode>(sb, cfg.dwords_per_lane, cfg.bytewise)
-                : mode == kDecode ? pick<kDecode>(sb, cfg.dwords_per_lane, cfg.bytewise)
-                                  : pick<kUpdate>(sb, cfg.dwords_per_lane, cfg.bytewise);
+  const int w = cfg.dwords_per_lane;
+  KernelFn fn;
+  switch (mode) {
+    case kEncode: fn = pick<kEncode>(sb, w, cfg.bytewise); break;
+    case kDecode: fn = pick<kDecode>(sb, w, cfg.bytewise); break;
+    case kUpdate: fn = pick<kUpdate>(sb, w, cfg.bytewise); break;
+    case kUpdateMatrix: fn = pick<kUpdateMatrix>(sb, w, cfg.bytewise); break;
+    default: return (int)hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0,
                      reinterpret_cast<hipStream_t>(stream), p);
   return (int)hipGetLastError();
@@ -877,13 +986,17 @@ int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
   if (err) return err;
   const int w = cfg.dwords_per_lane;
   BatchFn fn;
-  switch ((int)mode | (cfg.nibble ? kNibbleBit : 0)) {
+  // (the matrix-form update has no LFSR tables: the placement does not apply)
+  const bool nibble = cfg.nibble && mode != kUpdateMatrix;
+  switch ((int)mode | (nibble ? kNibbleBit : 0)) {
     case kEncode: fn = pick_batch<kEncode>(sb, w); break;
     case kDecode: fn = pick_batch<kDecode>(sb, w); break;
     case kUpdate: fn = pick_batch<kUpdate>(sb, w); break;
+    case kUpdateMatrix: fn = pick_batch<kUpdateMatrix>(sb, w); break;
     case kEncode | kNibbleBit: fn = pick_batch<kEncode | kNibbleBit>(sb, w); break;
     case kDecode | kNibbleBit: fn = pick_batch<kDecode | kNibbleBit>(sb, w); break;
-    default: fn = pick_batch<kUpdate | kNibbleBit>(sb, w); break;
+    case kUpdate | kNibbleBit: fn = pick_batch<kUpdate | kNibbleBit>(sb, w); break;
+    default: return (int)hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0, st, g);
   return (int)hipGetLastError();

@@ -104,7 +104,29 @@ int Code::init(int k, int m, int w, unsigned poly) {
     return v ^ ((uint64_t)f << (8 * (sb - 1)));
   };
   make_basis(sb, w, tval, lfsr_basis_);
+
+  // Generator-matrix columns (Sec. 6): x^m mod g = g_0 + ... + g_(m-1)
+  // x^(m-1) (characteristic 2), then one multiplication by x mod g per data
+  // block.
+  pcol_.assign((size_t)k * m, 0);
+  std::vector<uint8_t> r(g_, g_ + m);
+  for (int j = 0; j < k; ++j) {
+    memcpy(&pcol_[(size_t)j * m], r.data(), (size_t)m);
+    const uint8_t top = r[m - 1];
+    for (int i = m - 1; i >= 1; --i) r[i] = r[i - 1] ^ F_.mul(top, g_[i]);
+    r[0] = F_.mul(top, g_[0]);
+  }
   return RS_OK;
+}
+
+void Code::column_basis(int j, uint32_t *basis) const {
+  const uint8_t *col = &pcol_[(size_t)j * m_];
+  auto val = [this, col](uint8_t x) -> uint64_t {
+    uint64_t v = 0;
+    for (int b = 0; b < m_; ++b) v |= (uint64_t)F_.mul(col[m_ - 1 - b], x) << (8 * b);
+    return v;
+  };
+  make_basis(sb_, F_.w(), val, basis);
 }
 
 size_t Code::KeyHash::operator()(const Key &k) const {

@@ -64,6 +64,10 @@ class Code {
   const Field &field() const { return F_; }
   // Degree of API block b in the codeword polynomial (eq. (2)).
   int position(int b) const { return b < k_ ? m_ + b : b - k_; }
+  // Packed-table basis of the generator-matrix column of data block j
+  // (Sec. 6): byte x maps to the remainder of x * x^(m+j) mod g(x), byte b
+  // holding coefficient m-1-b.  16 dwords, as lfsr_basis().
+  void column_basis(int j, uint32_t *basis) const;
   // Plan for the erasure list e[0..t), validated and sorted increasingly by
   // the caller; rebuilt symbol i is block e[i].  Cached (Opt3 of Sec. 4).
   std::shared_ptr<const DecodePlan> plan(const int *e, int t, unsigned flags);
@@ -75,6 +79,7 @@ class Code {
   Field F_;
   uint8_t g_[kMaxM + 1] = {};
   uint32_t lfsr_basis_[16] = {};
+  std::vector<uint8_t> pcol_;   // k x m: row j = coefficients of x^(m+j) mod g
 
   // LRU cache of plans keyed by (erased-block bitmap, flags).
   struct Key {

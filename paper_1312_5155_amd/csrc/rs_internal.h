@@ -48,12 +48,17 @@ struct CodecParams {
   int32_t n_out;                  // blocks written
   const uint8_t *zero_page;       // kZeroPageBytes of zeros on the device
   uint32_t lfsr_basis[16];        // 8 values of T'(2^b), 1 or 2 dwords each
-  uint32_t apply_basis[kMaxM][16];// decode: per remainder byte, 8 values
+  uint32_t apply_basis[kMaxM][16];// decode: per remainder byte, 8 values;
+                                  // matrix update: per changed block
 };
 
 // kUpdate: parity ^= encode(delta) -- the encode LFSR over the changed data
-// blocks, plus the old parity read back in place.
-enum Mode : int { kEncode = 0, kDecode = 1, kUpdate = 2 };
+// blocks, plus the old parity read back in place.  kUpdateMatrix: the same
+// result from the generator-matrix columns of the (at most
+// kMatrixMaxBlocks) changed blocks, one packed lookup per changed block and
+// column; the apply bases then hold the columns' table bases.
+enum Mode : int { kEncode = 0, kDecode = 1, kUpdate = 2, kUpdateMatrix = 3 };
+constexpr int kMatrixMaxBlocks = 8;
 
 // A launch configuration of the codec kernel.
 struct LaunchCfg {

@@ -38,6 +38,14 @@ void fill_encode_params(const Code &c, const uint8_t *const *data, uint8_t *cons
 // block) hold the delta blocks or nullptr, parity is read and written in
 // place.
 int update_span(const Code &c, const uint8_t *const *delta);
+// Number of changed blocks; the first kMatrixMaxBlocks indices go to which.
+int update_changed(const Code &c, const uint8_t *const *delta, int *which);
+// Matrix-form update (n <= kMatrixMaxBlocks changed blocks which[0..n)):
+// data slot t holds the delta of block which[t], apply basis t its
+// generator-matrix column table.
+void fill_matrix_update_params(const Code &c, const uint8_t *const *delta,
+                               uint8_t *const *parity, const int *which, int n,
+                               uint64_t offset, uint64_t B, CodecParams *p);
 void fill_update_params(const Code &c, const uint8_t *const *delta, uint8_t *const *parity,
                         int span, uint64_t offset, uint64_t B, CodecParams *p);
 void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,

@@ -165,13 +165,13 @@ def test_update_sequence_tracks_the_data():
 
 # ------------------------------------------------------------- batched --
 
-def batch_cases(seed, count, codes, lo, hi):
+def batch_cases(seed, count, codes, lo, hi, max_changed=None):
     rng = workloads.meta_rng(seed)
     sizes = workloads.log_uniform_sizes(rng, count, lo, hi)
     cases = []
     for s in range(count):
         k, m = codes[int(rng.integers(0, len(codes)))]
-        n_changed = int(rng.integers(0, k + 1))
+        n_changed = int(rng.integers(0, min(k, max_changed or k) + 1))
         changed = rng.choice(k, size=n_changed, replace=False).tolist()
         # 256-byte aligned rows (the batch path needs 16-byte alignment)
         cases.append(UpdateCase(k, m, int(sizes[s]), changed, seed=seed * 1000 + s,
@@ -215,6 +215,33 @@ def test_batch_update_table_placements(placement):
     torch.cuda.synchronize()
     for c in cases:
         c.check()
+
+
+def test_batch_update_matrix_form_matches_oracle():
+    # at most 8 changed blocks per stripe: every width takes the
+    # generator-matrix form (one lookup per changed block)
+    say("batch update, matrix form")
+    cases = batch_cases(66, 40, ((6, 3), (10, 4), (12, 4), (32, 8), (5, 6), (3, 1)),
+                        1, 300000, max_changed=8)
+    bt = B.Batch()
+    bt.update(entries(cases))
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check()
+
+
+def test_plain_update_both_forms_at_the_boundary():
+    # 8 changed blocks (matrix form) and 9 (LFSR form) of RS(32,8) and
+    # RS(12,4), as the plain path chooses them
+    say("plain update, 8 and 9 changed blocks")
+    for k, m in ((32, 8), (12, 4)):
+        for n in (8, 9):
+            changed = list(range(0, k, max(1, k // n)))[:n]
+            assert len(set(changed)) == n and max(changed) < k
+            case = UpdateCase(k, m, 30001, changed, seed=k * 10 + n)
+            B.Code(k, m).update(case.delta_ptrs(), case.parity_ptrs(), 30001)
+            torch.cuda.synchronize()
+            case.check()
 
 
 def test_batch_update_equals_plain_update():
