@@ -115,7 +115,9 @@ int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data,
  * parity plus the encoding of the data difference.  For every byte column c,
  *     parity[i][c] ^= coefficient i of x^m * sum_j delta[j][c] x^j mod g(x),
  * in one pass that reads the delta blocks and the parity and writes the
- * parity in place.
+ * parity in place.  Up to 8 changed blocks use the generator-matrix columns
+ * x^(m+j) mod g(x) of Sec. 6 (one table lookup per changed block); more use
+ * the encode LFSR.  Both give the same bytes.
  *   delta    host array of k device pointers; delta[j] is the XOR of new and
  *            old data block j (read only), or NULL for an unchanged block,
  *            which is not read.  All NULL is a successful no-op.
@@ -239,8 +241,10 @@ int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
                          int count, void *stream);
 
 /* Delta-parity updates (as rs_poly_update) of every stripe, with one graph
- * launch per state width.  Every non-NULL block pointer must be 16-byte
- * aligned; the parity of different stripes must not overlap.
+ * launch per state width; a width uses the generator-matrix form when none
+ * of its stripes changes more than 8 blocks, else the LFSR form.  Every
+ * non-NULL block pointer must be 16-byte aligned; the parity of different
+ * stripes must not overlap.
  * Errors: RS_ENULL, RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
 int rs_poly_batch_update(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
                          int count, void *stream);

@@ -255,28 +255,47 @@ __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
   return t;
 }
 
+// Fills `tables` tables of `table_bytes` each (replicas of one 4- or 8-byte
+// entry) at byte `base` of rows 0..rows-1.  Thread idx computes entry
+// idx / tables of table idx mod tables once, as a (low, high) dword pair (the
+// same dword twice for 4-byte entries), and stores its 16-byte chunks
+// starting at chunk (row mod chunks): the lanes of a wave that share a table
+// but not a row then store to different banks.
+template <class ValueFn>
+__device__ __forceinline__ void fill_tables(uint8_t *lds, uint32_t rows, uint32_t base,
+                                            uint32_t tables, uint32_t table_bytes,
+                                            ValueFn value) {
+  const uint32_t chunks = table_bytes / 16;   // 2 or 4
+  for (uint32_t idx = threadIdx.x; idx < rows * tables; idx += blockDim.x) {
+    const uint32_t r = idx / tables, t = idx % tables;
+    const uint2 v = value(r, t);
+    const uint32_t at = r * kRowBytes + base + t * table_bytes;
+    for (uint32_t c = 0; c < chunks; ++c)
+      st4(lds, at + 16 * ((c + r) & (chunks - 1)), v.x, v.y, v.x, v.y);
+  }
+}
+
+template <int M>
+__device__ __forceinline__ uint2 entry_of(uint32_t f, const uint32_t *basis, int rot_bytes) {
+  if constexpr (M == 4) {
+    const uint32_t v = rotl32(lin32(f, basis), 8 * rot_bytes);
+    return make_uint2(v, v);
+  } else {
+    const uint64_t x = rotl64(lin64(f, basis), 8 * rot_bytes);
+    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+  }
+}
+
 // Expands the LFSR tables: copy v (0..M-1) of entry f is rotl(T'[f], 8(v+1));
 // split-nibble: row r < 16 holds entry r, row 16 + r entry r << 4.
 template <int M, int MODE>
 __device__ void build_lfsr_tables(uint8_t *lds, const uint32_t *basis) {
   using L = Layout<M, MODE>;
-  constexpr uint32_t kRows = L::kNibble ? 32 : 256;
-  for (uint32_t idx = threadIdx.x; idx < kRows * L::kCopies; idx += blockDim.x) {
-    const uint32_t r = idx / L::kCopies, v = idx % L::kCopies;
-    const uint32_t f = !L::kNibble ? r : r < 16 ? r : (r - 16) << 4;
-    const uint32_t base = r * kRowBytes + v * L::kCopyBytes;
-    uint32_t lo, hi;
-    if constexpr (M == 4) {
-      lo = hi = rotl32(lin32(f, basis), 8 * (v + 1));
-    } else {
-      const uint64_t x = rotl64(lin64(f, basis), 8 * (v + 1));
-      lo = (uint32_t)x;
-      hi = (uint32_t)(x >> 32);
-    }
-#pragma unroll
-    for (uint32_t r = 0; r < L::kCopyBytes / 16; ++r)
-      st4(lds, base + 16 * r, lo, hi, lo, hi);
-  }
+  fill_tables(lds, L::kNibble ? 32 : 256, 0, L::kCopies, L::kCopyBytes,
+              [&](uint32_t r, uint32_t v) {
+                const uint32_t f = !L::kNibble ? r : r < 16 ? r : (r - 16) << 4;
+                return entry_of<M>(f, basis, (int)v + 1);
+              });
 }
 
 // Expands the decode apply tables U'_b, b < m (unused tables are zero).
@@ -284,49 +303,27 @@ template <int M>
 __device__ void build_apply_tables(uint8_t *lds, const uint32_t *basis /* [kMaxM][16] */,
                                    int m) {
   using L = Layout<M, kDecode>;
-  for (uint32_t idx = threadIdx.x; idx < 256 * M; idx += blockDim.x) {
-    const uint32_t f = idx / M, b = idx % M;
-    const bool used = (int)b < m;
-    const uint32_t base = f * kRowBytes + L::kApplyBase + b * L::kTableBytes;
-    uint32_t lo, hi;
-    if constexpr (M == 4) {
-      lo = hi = used ? lin32(f, basis + 16 * b) : 0u;
-    } else {
-      const uint64_t x = used ? lin64(f, basis + 16 * b) : 0ull;
-      lo = (uint32_t)x;
-      hi = (uint32_t)(x >> 32);
-    }
-#pragma unroll
-    for (uint32_t r = 0; r < L::kTableBytes / 16; ++r) st4(lds, base + 16 * r, lo, hi, lo, hi);
-  }
+  fill_tables(lds, 256, L::kApplyBase, M, L::kTableBytes,
+              [&](uint32_t f, uint32_t b) {
+                return (int)b < m ? entry_of<M>(f, basis + 16 * b, 0) : make_uint2(0u, 0u);
+              });
 }
 
 // Expands the matrix-update tables.  Window position pos (item pos / M,
-// slot pos mod M) holds changed block t = k_pad - 1 - pos, as load_item
-// places it; tables of positions with no block are zero.
+// slot pos mod M; its table at byte pos * kMatTableBytes of the row) holds
+// changed block t = k_pad - 1 - pos, as load_item places it; tables of
+// positions with no block are zero.
 template <int M>
 __device__ void build_matrix_tables(uint8_t *lds, const uint32_t *basis /* [kMaxM][16] */,
                                     int c, int k_pad) {
   using L = Layout<M, kUpdateMatrix>;
-  static_assert(kRowBytes / L::kMatGroupBytes * M == kMatrixMaxBlocks, "one row holds all tables");
-  for (uint32_t idx = threadIdx.x; idx < 256 * kMatrixMaxBlocks; idx += blockDim.x) {
-    const uint32_t f = idx / kMatrixMaxBlocks, pos = idx % kMatrixMaxBlocks;
+  static_assert(L::kMatGroupBytes == M * L::kMatTableBytes &&
+                    kMatrixMaxBlocks * L::kMatTableBytes == kRowBytes,
+                "one row holds all tables, position after position");
+  fill_tables(lds, 256, 0, kMatrixMaxBlocks, L::kMatTableBytes, [&](uint32_t f, uint32_t pos) {
     const int tt = k_pad - 1 - (int)pos;
-    const bool used = tt >= 0 && tt < c;
-    const uint32_t base =
-        f * kRowBytes + (pos / M) * L::kMatGroupBytes + (pos % M) * L::kMatTableBytes;
-    uint32_t lo, hi;
-    if constexpr (M == 4) {
-      lo = hi = used ? lin32(f, basis + 16 * tt) : 0u;
-    } else {
-      const uint64_t x = used ? lin64(f, basis + 16 * tt) : 0ull;
-      lo = (uint32_t)x;
-      hi = (uint32_t)(x >> 32);
-    }
-#pragma unroll
-    for (uint32_t r = 0; r < L::kMatTableBytes / 16; ++r)
-      st4(lds, base + 16 * r, lo, hi, lo, hi);
-  }
+    return tt >= 0 && tt < c ? entry_of<M>(f, basis + 16 * tt, 0) : make_uint2(0u, 0u);
+  });
 }
 
 // Block pointers always address global memory; saying so keeps the
