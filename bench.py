@@ -398,7 +398,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30,
+                    help="untimed steps first (the clocks settle over the first tens)")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=48,
                     help="stripes the CPU oracle encodes+decodes (0 = skip)")

@@ -247,8 +247,17 @@ struct GroupPlan {
   std::vector<uint32_t> apply;  // kMaxM*16 per set
   std::unordered_map<const Code *, uint32_t> lfsr_index;
   std::unordered_map<const DecodePlan *, uint32_t> apply_index;
-  // matrix-form update: table bases per (code, changed-block set)
-  std::map<std::pair<const Code *, std::vector<int>>, uint32_t> matrix_index;
+  // matrix-form update: table bases per (code, changed-block set); the set
+  // is packed one index per byte (at most 8 indices below 255, count apart)
+  struct MatrixKey {
+    const Code *code;
+    uint64_t packed;
+    int n;
+    bool operator<(const MatrixKey &o) const {
+      return std::tie(code, packed, n) < std::tie(o.code, o.packed, o.n);
+    }
+  };
+  std::map<MatrixKey, uint32_t> matrix_index;
   bool matrix = false;   // update group in the generator-matrix form
   std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
   uint64_t tiles = 0;
@@ -351,7 +360,8 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     int which[kMatrixMaxBlocks];
     const int changed = op == RS_POLY_OP_UPDATE ? update_changed(c, st.blocks, which) : 0;
     if (gp.matrix) {
-      std::pair<const Code *, std::vector<int>> key{&c, std::vector<int>(which, which + changed)};
+      GroupPlan::MatrixKey key{&c, 0, changed};
+      for (int t = 0; t < changed; ++t) key.packed |= (uint64_t)which[t] << (8 * t);
       auto mi = gp.matrix_index.find(key);
       if (mi == gp.matrix_index.end()) {
         mi = gp.matrix_index.emplace(key, (uint32_t)(gp.apply.size() / (kMaxM * 16))).first;
