@@ -70,10 +70,10 @@ rs_poly_launch_t default_launch(int op, int wide) {
   } else {
     c.bytes_per_lane = 16;
     c.threads = 512;
-    c.tile_bytes = 16 << 10;
+    c.tile_bytes = op == RS_POLY_OP_ENCODE ? 8 << 10 : 16 << 10;
   }
   // (a wide decode workgroup takes 128 KiB of LDS: one fits per CU)
-  c.wgs_per_cu = wide ? (op == RS_POLY_OP_DECODE ? 1 : 2) : (op == RS_POLY_OP_DECODE ? 2 : 1);
+  c.wgs_per_cu = wide && op == RS_POLY_OP_DECODE ? 1 : 2;
   c.table_placement = RS_POLY_TABLES_PACKED;
   return c;
 }
@@ -682,7 +682,7 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
     std::vector<rs_poly_launch_t> cands;
     for (int bpl : {4, 8, 16})
       for (int th : {256, 512, 1024})
-        for (int tile : {16 << 10, 64 << 10, 256 << 10})
+        for (int tile : {8 << 10, 16 << 10, 64 << 10, 256 << 10})
           for (int wgs = 1; wgs <= 2; ++wgs)
             for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE}) {
               const rs_poly_launch_t c{bpl, th, tile, wgs, tp};
