@@ -50,13 +50,15 @@
 // lane's replica offset, so one v_perm_b32 of (state, lane offset) yields
 // the address (M = 4; a v_perm and an OR for M = 8).  Replicas spread the
 // lanes of a wave over banks, and lanes start at different rotation phases,
-// so that one read spreads over all copies.  64 KiB per workgroup, two workgroups
-// per CU (128 KiB and one workgroup for the decode of m > 4).
+// so that one read spreads over all copies.  64 KiB per workgroup (8 KiB for
+// split-nibble encode/update tables; 128 KiB, one workgroup per CU, for the
+// decode of m > 4).
 //
 // Memory-level parallelism.  The kernels stream every byte once; throughput
-// is set by the bytes in flight per CU.  Each lane walks its column chunks
-// as a software pipeline that keeps the loads of the next M blocks in
-// flight while the current M are absorbed.
+// is set by the bytes in flight per CU and by how local the concurrent
+// accesses are.  Each lane walks its column chunks as a software pipeline
+// that keeps the loads of the next M blocks in flight while the current M
+// are absorbed.
 #include <hip/hip_runtime.h>
 
 #include "rs_internal.h"

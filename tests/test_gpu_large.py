@@ -1,0 +1,82 @@
+"""Blocks larger than 2 GiB: the kernels address columns with 32-bit
+offsets, so the library splits such blocks into column ranges (plain and
+batched path).  The results are checked against the oracle on column
+windows around the split point and at both ends, and the batched, plain,
+decode and update paths against each other on the whole blocks."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_1312_5155_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+K, M = 3, 2
+NB = (1 << 31) + 4096 + 17          # over 2 GiB, ragged tail
+NBP = (NB + 255) // 256 * 256       # row stride: 16-byte aligned rows
+WINDOWS = [(0, 1 << 16), ((1 << 31) - (1 << 15), (1 << 31) + (1 << 15)), (NB - (1 << 16), NB)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def stripe():
+    # k data blocks, m parity blocks and m more for the batched result
+    rows = torch.zeros((K + 2 * M, NBP), dtype=torch.uint8, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.data_seed(9))
+    for j in range(K):
+        rows[j, :NB] = torch.randint(0, 256, (NB,), dtype=torch.uint8, device="cuda",
+                                     generator=gen)
+    yield rows
+    del rows
+    torch.cuda.empty_cache()
+
+
+def check_windows(rows, parity_rows):
+    F = oracle.Field(8, 0x11D)
+    for lo, hi in WINDOWS:
+        d = rows[:K, lo:hi].cpu().numpy()
+        p = rows[parity_rows, lo:hi].cpu().numpy()
+        assert np.array_equal(p, oracle.encode(F, K, M, d)), (lo, hi)
+
+
+def test_encode_over_2GiB_plain_and_batched(stripe):
+    say(f"encode RS({K},{M}) blocks of {NB} bytes")
+    code = B.Code(K, M)
+    ptr = [stripe[b].data_ptr() for b in range(K + 2 * M)]
+    code.encode(ptr[:K], ptr[K:K + M], NB)
+    torch.cuda.synchronize()
+    check_windows(stripe, list(range(K, K + M)))
+    bt = B.Batch()
+    bt.encode([(code, ptr[:K] + ptr[K + M:], NB)])
+    torch.cuda.synchronize()
+    assert torch.equal(stripe[K:K + M, :NB], stripe[K + M:, :NB])
+
+
+def test_decode_and_update_over_2GiB(stripe):
+    say("decode and update over 2 GiB")
+    code = B.Code(K, M)
+    ptr = [stripe[b].data_ptr() for b in range(K + M)]
+    lost = [1, K]                      # a data block and a parity block
+    saved = stripe[lost, :NB].clone()
+    stripe[lost, :NB] = 0x5A
+    code.decode(ptr, lost, NB)
+    torch.cuda.synchronize()
+    assert torch.equal(stripe[lost, :NB], saved)
+    del saved
+    # update block 2 by a delta, batched; then check windows of the new data
+    delta = torch.randint(0, 256, (NB,), dtype=torch.uint8, device="cuda")
+    bt = B.Batch()
+    bt.update([(code, [None, None, delta.data_ptr()] + ptr[K:], NB)])
+    stripe[2, :NB] ^= delta
+    torch.cuda.synchronize()
+    check_windows(stripe, list(range(K, K + M)))
