@@ -40,7 +40,9 @@ struct GroupBuf {
   uint64_t version = 0;           // bumped when device buffers move
 };
 
-using GraphKey = std::tuple<int, int, int, int, int, int, uint64_t>;
+// (op, width, bytes per lane, threads, WGs per CU, table placement, staging
+// buffer, buffer version)
+using GraphKey = std::tuple<int, int, int, int, int, int, int, uint64_t>;
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
@@ -90,10 +92,12 @@ struct rs_poly_batch {
   std::string arch;
   hipStream_t capture = nullptr;
   GroupBuf groups[kWidths];
-  // Two pinned staging buffers used in turn; each event marks the end of
-  // the upload from that buffer, so the host rarely waits to refill one.
-  uint8_t *staging[2] = {nullptr, nullptr};
-  size_t staging_bytes[2] = {0, 0};
+  // Two coherent pinned staging buffers per width, used in turn.  The pull
+  // kernel of the call's graph reads them; each event marks the end of the
+  // call that read buffer pair i, so the host rarely waits to refill one.
+  uint8_t *staging[kWidths][2] = {};
+  size_t staging_bytes[kWidths][2] = {};
+  const uint8_t *staging_dev[kWidths][2] = {};
   hipEvent_t staging_free[2] = {nullptr, nullptr};
   bool staging_pending[2] = {false, false};
   int staging_next = 0;
@@ -106,12 +110,14 @@ struct rs_poly_batch {
   // Device and pinned buffers replaced by larger ones; kernels queued earlier
   // may still read them, so they are freed with the object.
   std::vector<void *> retired_dev, retired_host;
+  std::vector<GraphEntry> retired_graphs;
 
   ~rs_poly_batch();
   void drop_graphs();
-  int ensure_staging(int i, size_t bytes);
+  void drop_graphs_of(int wide);
+  int ensure_staging(int i, const size_t *bytes);
   int ensure_group(int wide, size_t arena_bytes, uint64_t tiles, uint32_t stripes);
-  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, hipGraphExec_t *out);
+  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, hipGraphExec_t *out);
   int run(int op, const rs_poly_stripe_t *stripes, int count, void *stream);
 };
 
@@ -123,16 +129,34 @@ void rs_poly_batch::drop_graphs() {
   graphs.clear();
 }
 
+// Graphs of one width stop being used when its buffers move; launches of
+// them may still be queued, so they are destroyed with the object.
+void rs_poly_batch::drop_graphs_of(int wide) {
+  for (auto it = graphs.begin(); it != graphs.end();) {
+    if (std::get<1>(it->first) == wide) {
+      retired_graphs.push_back(it->second);
+      it = graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 rs_poly_batch::~rs_poly_batch() {
   for (int i = 0; i < 2; ++i)
     if (staging_pending[i]) (void)hipEventSynchronize(staging_free[i]);
   drop_graphs();
+  for (auto &e : retired_graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
   for (auto &g : groups) {
     if (g.arena) (void)hipFree(g.arena);
     if (g.tile_stripe) (void)hipFree(g.tile_stripe);
   }
   for (int i = 0; i < 2; ++i) {
-    if (staging[i]) (void)hipHostFree(staging[i]);
+    for (int w = 0; w < kWidths; ++w)
+      if (staging[w][i]) (void)hipHostFree(staging[w][i]);
     if (staging_free[i]) (void)hipEventDestroy(staging_free[i]);
   }
   for (void *p : retired_dev) (void)hipFree(p);
@@ -141,21 +165,31 @@ rs_poly_batch::~rs_poly_batch() {
   if (capture) (void)hipStreamDestroy(capture);
 }
 
-// Makes staging buffer i hold at least `bytes` and be free to overwrite.
-int rs_poly_batch::ensure_staging(int i, size_t bytes) {
+// Makes staging buffer pair i hold at least bytes[w] for each width and be
+// free to overwrite.  The buffers are coherent (the device reads what the
+// host wrote before the launch); a replaced buffer is retired and the
+// graphs that read it are dropped.
+int rs_poly_batch::ensure_staging(int i, const size_t *bytes) {
   if (staging_pending[i]) {
     if (hipEventSynchronize(staging_free[i]) != hipSuccess) return RS_EDEVICE;
     staging_pending[i] = false;
   }
-  if (bytes <= staging_bytes[i]) return RS_OK;
-  if (staging[i]) retired_host.push_back(staging[i]);
-  staging[i] = nullptr;
-  staging_bytes[i] = 0;
-  const size_t want = align_up(bytes + bytes / 2, 1 << 16);
-  if (hipHostMalloc(reinterpret_cast<void **>(&staging[i]), want, hipHostMallocDefault) !=
-      hipSuccess)
-    return RS_ENOMEM;
-  staging_bytes[i] = want;
+  for (int w = 0; w < kWidths; ++w) {
+    if (bytes[w] <= staging_bytes[w][i]) continue;
+    if (staging[w][i]) retired_host.push_back(staging[w][i]);
+    staging[w][i] = nullptr;
+    staging_dev[w][i] = nullptr;
+    staging_bytes[w][i] = 0;
+    drop_graphs_of(w);
+    const size_t want = align_up(bytes[w] + bytes[w] / 2, 1 << 16);
+    if (hipHostMalloc(reinterpret_cast<void **>(&staging[w][i]), want,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+      return RS_ENOMEM;
+    void *dev = nullptr;
+    if (hipHostGetDevicePointer(&dev, staging[w][i], 0) != hipSuccess) return RS_EDEVICE;
+    staging_dev[w][i] = static_cast<const uint8_t *>(dev);
+    staging_bytes[w][i] = want;
+  }
   return RS_OK;
 }
 
@@ -182,24 +216,15 @@ int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
   g.tile_cap = new_tiles;
   g.stripe_cap = new_stripes;
   ++g.version;
-  // Graphs of this group hold the old pointers.
-  for (auto it = graphs.begin(); it != graphs.end();) {
-    if (std::get<1>(it->first) == wide) {
-      (void)hipGraphExecDestroy(it->second.exec);
-      (void)hipGraphDestroy(it->second.graph);
-      it = graphs.erase(it);
-    } else {
-      ++it;
-    }
-  }
+  drop_graphs_of(wide);   // they hold the old pointers
   return RS_OK;
 }
 
-int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
+int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si,
                              hipGraphExec_t *out) {
   GroupBuf &gb = groups[wide];
-  const GraphKey key{op,          wide,           cfg.bytes_per_lane, cfg.threads,
-                     cfg.wgs_per_cu, cfg.table_placement, gb.version};
+  const GraphKey key{op,          wide, cfg.bytes_per_lane, cfg.threads, cfg.wgs_per_cu,
+                     cfg.table_placement, si, gb.version};
   auto it = graphs.find(key);
   if (it != graphs.end()) {
     *out = it->second.exec;
@@ -207,7 +232,7 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg,
   }
   const uint8_t *zp = device_zero_page();
   if (!zp) return RS_EDEVICE;
-  BatchGroup g{gb.arena, gb.tile_stripe, zp};
+  BatchGroup g{gb.arena, gb.tile_stripe, zp, staging_dev[wide][si]};
   LaunchCfg lc{};
   lc.dwords_per_lane = cfg.bytes_per_lane / 4;
   lc.threads = cfg.threads;
@@ -425,7 +450,6 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
 
   // Tiles per stripe depend on the launch shape of the group.
   size_t total_upload = 0;
-  size_t upload_at[kWidths] = {0, 0};
   size_t upload_len[kWidths] = {0, 0};
   size_t offs[kWidths][4];
   for (int w = 0; w < kWidths; ++w) {
@@ -447,7 +471,6 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     }
     gp.tiles = t;
     upload_len[w] = gp.layout(&offs[w][0], &offs[w][1], &offs[w][2], &offs[w][3]);
-    upload_at[w] = total_upload;
     total_upload += upload_len[w];
   }
   if (total_upload == 0) return RS_OK;
@@ -460,15 +483,16 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   }
   const int si = staging_next;
   staging_next ^= 1;
-  int rc = ensure_staging(si, total_upload);
+  int rc = ensure_staging(si, upload_len);
   if (rc != RS_OK) return rc;
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   for (int w = 0; w < kWidths; ++w) {
     GroupPlan &gp = plan[w];
     if (gp.descs.empty()) continue;
-    uint8_t *h = staging[si] + upload_at[w];
+    uint8_t *h = staging[w][si];
     BatchHeader hdr{};
+    hdr.upload_bytes = upload_len[w];
     hdr.total_tiles = gp.tiles;
     hdr.n_stripes = (uint32_t)gp.descs.size();
     hdr.tile_cols = gp.tile_cols;
@@ -486,21 +510,16 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   // The arena may still be read by the previous call's kernels if that call
   // went to another stream.
   if (last_done_valid && hipStreamWaitEvent(st, last_done, 0) != hipSuccess) return RS_EDEVICE;
-  for (int w = 0; w < kWidths; ++w) {
-    if (plan[w].descs.empty()) continue;
-    if (hipMemcpyAsync(groups[w].arena, staging[si] + upload_at[w], upload_len[w],
-                       hipMemcpyHostToDevice, st) != hipSuccess)
-      return RS_EDEVICE;
-  }
-  if (hipEventRecord(staging_free[si], st) != hipSuccess) return RS_EDEVICE;
-  staging_pending[si] = true;
+  // Each group's graph pulls its upload from the staging pair si first.
   for (int w = 0; w < kWidths; ++w) {
     if (plan[w].descs.empty()) continue;
     hipGraphExec_t exec;
-    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], &exec);
+    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], si, &exec);
     if (rc != RS_OK) return rc;
     if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
   }
+  if (hipEventRecord(staging_free[si], st) != hipSuccess) return RS_EDEVICE;
+  staging_pending[si] = true;
   if (hipEventRecord(last_done, st) != hipSuccess) return RS_EDEVICE;
   last_done_valid = true;
   return RS_OK;
@@ -572,8 +591,9 @@ int rs_poly_batch_reserve(rs_poly_batch_t *b, int max_stripes, size_t max_block_
     const int rc = b->ensure_group(w, arena, tiles, (uint32_t)descs);
     if (rc != RS_OK) return rc;
   }
+  const size_t want[kWidths] = {arena, arena};
   for (int i = 0; i < 2; ++i) {
-    const int rc = b->ensure_staging(i, 2 * arena);
+    const int rc = b->ensure_staging(i, want);
     if (rc != RS_OK) return rc;
   }
   return RS_OK;

@@ -828,6 +828,20 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
+// Copies a group's upload (header, descriptors, pointers, table bases) from
+// coherent pinned host memory to the arena, 16 bytes per thread and step.
+// The size is in the upload's own header.  Reading the host copy from the
+// graph's first kernel keeps the upload on the launch queue.
+__global__ void batch_pull_kernel(BatchGroup g) {
+  const uint64_t bytes = reinterpret_cast<const BatchHeader *>(g.host_src)->upload_bytes;
+  const uint4 *src = reinterpret_cast<const uint4 *>(g.host_src);
+  uint4 *dst = reinterpret_cast<uint4 *>(g.arena);
+  const uint64_t n = bytes / 16;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Fills the tile -> stripe map of a batch group (one thread per tile, a
 // binary search over the stripes' first tiles) and clears the tile counter;
 // runs before the persistent kernel in the same graph.  The grid covers the
@@ -977,6 +991,9 @@ int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, 
 int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
                  const LaunchCfg &cfg, void *stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(batch_pull_kernel, dim3(64), dim3(256), 0, st, g);
+  int perr = (int)hipGetLastError();
+  if (perr) return perr;
   const uint32_t prep_threads = 256;
   const uint32_t prep_grid = (uint32_t)((max_tiles + prep_threads - 1) / prep_threads);
   hipLaunchKernelGGL(batch_prepare_kernel, dim3(prep_grid ? prep_grid : 1), dim3(prep_threads),

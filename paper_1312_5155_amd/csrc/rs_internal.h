@@ -92,6 +92,7 @@ struct StripeDesc {
 // per call and located by the byte offsets below, so one host-to-device copy
 // uploads a whole batch and captured graphs never need new arguments.
 struct BatchHeader {
+  uint64_t upload_bytes; // bytes of this group's packed upload (header included)
   uint64_t total_tiles;
   uint64_t counter;      // next tile to hand out; cleared by the prepare kernel
   uint32_t n_stripes;
@@ -106,15 +107,17 @@ struct BatchGroup {            // device pointers
   uint8_t *arena;              // BatchHeader, then the packed regions
   uint32_t *tile_stripe;       // tile -> stripe, filled by the prepare kernel
   const uint8_t *zero_page;    // kZeroPageBytes of zeros
+  const uint8_t *host_src;     // coherent pinned host copy of the upload
 };
 
 // kZeroPageBytes of zeros on the current device, allocated and cleared on
 // first use (per device, kept until the process ends); nullptr on error.
 const uint8_t *device_zero_page();
 
-// Enqueues the prepare kernel and the persistent batch kernel for a group
-// (max_tiles, the tile-map capacity, sizes the prepare grid).  Returns a
-// hipError_t as int.
+// Enqueues, for a group: the pull kernel (copies the upload from host_src to
+// the arena), the prepare kernel and the persistent batch kernel.  max_tiles
+// (the tile-map capacity) sizes the prepare grid.  Returns a hipError_t as
+// int.
 int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint64_t max_tiles,
                  const LaunchCfg &cfg, void *stream);
 
