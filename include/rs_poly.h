@@ -198,6 +198,9 @@ typedef struct rs_poly_launch {
     int wgs_per_cu;       /* persistent workgroups per CU: 1 or 2              */
     int table_placement;  /* LFSR tables in LDS: RS_POLY_TABLES_PACKED or      *
                            * RS_POLY_TABLES_NIBBLE                             */
+    int tile_order;       /* 0: tiles handed out in order (the workgroups work *
+                           * on neighbouring tiles); 1: each workgroup walks   *
+                           * its own run of tiles (dynamic claims either way)  */
 } rs_poly_launch_t;
 
 /* Table placements of the LFSR feedback products T[f] (both give identical
@@ -266,7 +269,7 @@ int rs_poly_batch_set_launch(rs_poly_batch_t *b, int op, int wide,
                              const rs_poly_launch_t *cfg);
 
 /* Autotuner: times every candidate launch shape (bytes per lane, threads,
- * tile, workgroups per CU, table placement) on these stripes (running
+ * tile, workgroups per CU, table placement, tile order) on these stripes (running
  * the real operation several times on `stream`: encode and decode are
  * idempotent, and an update runs an even number of times per candidate, so
  * the parity ends as it began -- tuning does not apply the update),

@@ -140,7 +140,7 @@ class Launch(ctypes.Structure):
     """rs_poly_launch_t."""
     _fields_ = [("bytes_per_lane", ctypes.c_int), ("threads", ctypes.c_int),
                 ("tile_bytes", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
-                ("table_placement", ctypes.c_int)]
+                ("table_placement", ctypes.c_int), ("tile_order", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -864,11 +864,12 @@ __global__ void batch_prepare_kernel(BatchGroup g) {
 }
 
 // Persistent kernel over every tile of a batch group.  Each workgroup takes
-// the next tile from an atomic counter (prefetched one tile ahead), finds
-// its stripe through the tile map, re-expands the LDS tables only when the
-// stripe's code, erasure pattern or changed-block set differs from the one
-// staged, and encodes, decodes or updates the tile's columns.  Every wave
-// leaves the loop once the counter passes the last tile.
+// the next claim from an atomic counter (prefetched one claim ahead), maps
+// it to a tile, finds the tile's stripe through the tile map, re-expands the
+// LDS tables only when the stripe's code, erasure pattern or changed-block
+// set differs from the one staged, and encodes, decodes or updates the
+// tile's columns.  Every wave leaves the loop once the counter passes the
+// last claim.
 template <int M, int W, int MODE>
 __global__ void __launch_bounds__((max_threads<M, W, MODE>()))
 __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) {
@@ -887,17 +888,28 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
   const Lanes<M, MODE> lt = make_lanes<M, MODE>();
   uint32_t staged_lfsr = ~0u, staged_apply = ~0u;
 
-  // Tiles are handed out in order, so the workgroups work on neighbouring
-  // tiles at any moment (measured faster than giving each workgroup its own
-  // run of tiles, which would restage its tables less often).
+  // Claim c maps to tile c (order 0: at any moment the workgroups work on
+  // neighbouring tiles) or to tile (c mod P) * run + c / P (order 1: a
+  // workgroup's successive claims, about P apart, are neighbouring tiles of
+  // its own run).  Which is faster depends on the workload; the order is a
+  // launch parameter.  Claims past the last tile are skipped.
+  const bool runs = chdr->tile_order != 0;
+  const uint64_t P = gridDim.x;
+  const uint64_t run = (total + P - 1) / P;
+  const uint64_t claims = runs ? run * P : total;
   if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
   __syncthreads();
   for (;;) {
-    const uint64_t tile =
+    const uint64_t c =
         (uint64_t)uniform((uint32_t)(next_claim >> 32)) << 32 | uniform((uint32_t)next_claim);
     __syncthreads();   // every thread has read next_claim
-    if (tile >= total) break;
+    if (c >= claims) break;
     if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
+    const uint64_t tile = runs ? (c % P) * run + c / P : c;
+    if (tile >= total) {
+      __syncthreads();   // next_claim is about to change
+      continue;
+    }
 
     const uint32_t s = tile_stripe[tile];
     const StripeDesc d = load_desc(descs + s);

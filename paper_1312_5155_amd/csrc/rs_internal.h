@@ -97,6 +97,8 @@ struct BatchHeader {
   uint64_t counter;      // next tile to hand out; cleared by the prepare kernel
   uint32_t n_stripes;
   uint32_t tile_cols;    // columns per tile for this call, multiple of 16
+  uint32_t tile_order;   // 0: tiles in order; 1: each workgroup walks a run
+  uint32_t pad_;
   uint64_t off_descs;    // StripeDesc[n_stripes]
   uint64_t off_ptrs;     // uint64_t device pointers
   uint64_t off_lfsr;     // 16 dwords per LFSR basis set

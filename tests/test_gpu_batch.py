@@ -168,8 +168,9 @@ def test_graph_replays_with_new_descriptors():
 @pytest.mark.parametrize("bpl", [4, 8, 16])
 @pytest.mark.parametrize("threads", [256, 1024])
 @pytest.mark.parametrize("placement", [B.RS_POLY_TABLES_PACKED, B.RS_POLY_TABLES_NIBBLE])
-def test_every_launch_shape(bpl, threads, placement):
-    say(f"launch shape bpl={bpl} threads={threads} placement={placement}")
+@pytest.mark.parametrize("order", [0, 1])
+def test_every_launch_shape(bpl, threads, placement, order):
+    say(f"launch shape bpl={bpl} threads={threads} placement={placement} order={order}")
     shapes = mixed_shapes(7, 12, ((10, 4), (6, 3), (32, 8), (5, 6)), 1, 70_000)
     arena = Arena(shapes)
     host = fill_data(arena, 21)
@@ -178,7 +179,7 @@ def test_every_launch_shape(bpl, threads, placement):
         # register-bound workgroup limits of the 16-byte-per-lane variants
         th = min(threads, (256 if wide else 512) if bpl == 16 else 1024)
         cfg = dict(bytes_per_lane=bpl, threads=th, tile_bytes=4096 * (1 + wide),
-                   wgs_per_cu=1 + wide, table_placement=placement)
+                   wgs_per_cu=1 + wide, table_placement=placement, tile_order=order)
         bt.set_launch(B.RS_POLY_OP_ENCODE, wide, cfg)
         # the wide decode: at most 8 bytes per lane, 512 threads at 8
         dbpl = min(bpl, 8) if wide else bpl
@@ -204,6 +205,8 @@ def test_set_launch_validation():
     bad = [dict(bytes_per_lane=3, threads=256, tile_bytes=4096, wgs_per_cu=1),
            dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
                 table_placement=2),
+           dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
+                tile_order=2),
            dict(bytes_per_lane=16, threads=300, tile_bytes=4096, wgs_per_cu=1),
            dict(bytes_per_lane=16, threads=256, tile_bytes=4000, wgs_per_cu=1),
            dict(bytes_per_lane=16, threads=256, tile_bytes=4096, wgs_per_cu=3)]
