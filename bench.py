@@ -255,6 +255,17 @@ def cpu_baseline(host_stripes, erasures, threads):
     return user / dt / 1e9, dt, parity
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def median(xs):
     xs = sorted(xs)
     n = len(xs)
@@ -601,11 +612,17 @@ def main():
         host = [buf[s, :K].cpu().numpy() for s in range(n)]
         threads = min(16, os.cpu_count() or 1)
         gbs, secs, want = cpu_baseline(host, erasures[:n], threads)
+        # one core, on the first few of the same stripes
+        n1 = min(3, n)
+        gbs1, secs1, _ = cpu_baseline(host[:n1], erasures[:n1], 1)
         # the GPU's parity of the sampled stripes against the oracle's
         exact = all((buf[s, K:].cpu().numpy() == want[s]).all() for s in range(n))
         cpu = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
                "sample": f"{n} of the {STRIPES} stripes, encode + decode each "
                          f"({secs:.1f} s wall on {threads} threads)",
+               "single_core": {"value": round(gbs1, 3), "sample": f"{n1} stripes, "
+                               f"{secs1:.1f} s"},
+               "cpu_model": cpu_model(),
                "gpu_parity_matches_oracle": bool(exact)}
         if not exact:
             raise SystemExit("GPU parity differs from the oracle on the CPU sample")
