@@ -137,9 +137,12 @@ int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta,
  *   n_erasures  t, 0 <= t <= m; t = 0 is a successful no-op
  *   flags       0 or RS_POLY_FLAG_ALL_SURVIVORS
  * Erased buffers are outputs only and are never read.  By default the
- * library reads k survivors (all surviving data blocks first, then the
- * lowest-numbered surviving parity blocks) and may leave the other m - t
- * surviving blocks unread; their pointers may then be NULL.
+ * library reads the k survivors of lowest degree in the code polynomial
+ * (every surviving parity block, p_i at degree i, then the surviving data
+ * blocks from d_0 up, d_j at degree m + j) and leaves the other m - t
+ * surviving blocks, the highest data blocks, unread; their pointers may then
+ * be NULL.  The LFSR starts at the highest data block read, so the unread
+ * blocks cost neither traffic nor steps.
  * Errors: RS_ENULL, RS_EINVAL (n_erasures < 0, unknown flags),
  * RS_ETOOMANY (t > m), RS_ERANGE, RS_EDEVICE. */
 int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,

@@ -170,9 +170,9 @@ void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *b
   }
   for (int r = 0; r < t; ++r) p->out[r] = blocks[sorted[r]] + offset;
   p->block_bytes = B;
-  p->k = c.k();
+  p->k = plan.span;   // data blocks above the span are unread
   p->m = c.m();
-  p->k_pad = round_up(c.k(), c.state_bytes());
+  p->k_pad = round_up(plan.span, c.state_bytes());
   p->n_out = t;
   memcpy(p->lfsr_basis, c.lfsr_basis(), sizeof(p->lfsr_basis));
   memcpy(p->apply_basis, plan.apply_basis, sizeof(p->apply_basis));

@@ -373,7 +373,11 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     const int rc = check_stripe(op, st, sorted, &dp);
     if (rc != RS_OK) return rc;
     const Code &c = st.code->code;
-    const int span = op == RS_POLY_OP_UPDATE ? update_span(c, st.blocks) : c.k();
+    // blocks the LFSR spans: update from the highest changed block, decode
+    // from the highest data block read
+    const int span = op == RS_POLY_OP_UPDATE ? update_span(c, st.blocks)
+                     : op == RS_POLY_OP_DECODE && dp ? dp->span
+                                                     : c.k();
     if (st.block_bytes == 0 || (op == RS_POLY_OP_DECODE && st.n_erasures == 0) || span == 0)
       continue;
     const int wide = c.state_bytes() == 8;
@@ -417,8 +421,9 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     for (uint64_t off = 0; off < st.block_bytes; off += kMaxPieceBytes) {
       StripeDesc d{};
       d.block_bytes = std::min<uint64_t>(kMaxPieceBytes, st.block_bytes - off);
-      // update: the LFSR starts at the highest changed block; the matrix
-      // form reads the changed blocks only
+      // the LFSR starts at block span - 1 (update: the highest changed
+      // block; decode: the highest data block read); the matrix form reads
+      // the changed blocks only
       const int kk = gp.matrix ? changed : span;
       d.k = kk;
       d.m = m;
@@ -444,10 +449,10 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
         const int t = st.n_erasures;
         d.n_out = t;
         const size_t base = gp.ptrs.size();
-        gp.ptrs.resize(base + k + m + t, 0);
-        // data d_j at entry j, parity p_i at entry k + i: entry b for block b
-        for (int b : dp->read) gp.ptrs[base + b] = at(b);
-        for (int r = 0; r < t; ++r) gp.ptrs[base + k + m + r] = at(sorted[r]);
+        gp.ptrs.resize(base + kk + m + t, 0);
+        // data d_j (j < span) at entry j, parity p_i at entry span + i
+        for (int b : dp->read) gp.ptrs[base + (b < k ? b : kk + b - k)] = at(b);
+        for (int r = 0; r < t; ++r) gp.ptrs[base + kk + m + r] = at(sorted[r]);
       }
       gp.descs.push_back(d);
     }

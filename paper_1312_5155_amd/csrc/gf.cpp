@@ -143,23 +143,27 @@ std::shared_ptr<DecodePlan> Code::build_plan(const int *e, int t, unsigned flags
   std::vector<char> erased(n, 0);
   for (int i = 0; i < t; ++i) erased[e[i]] = 1;
 
-  // Blocks read: every survivor, or (default) the surviving data blocks and
-  // then the lowest-numbered surviving parity blocks up to k in total.
-  int data_surv = 0;
-  for (int b = 0; b < k_; ++b) data_surv += !erased[b];
-  int parity_needed = (flags & RS_POLY_FLAG_ALL_SURVIVORS) ? m_ : k_ - data_surv;
+  // Blocks read: every survivor, or (default) the k survivors of lowest
+  // degree in the code polynomial -- the surviving parity blocks (degrees
+  // 0..m-1), then the surviving data blocks from d_0 up.  The LFSR then
+  // starts at the highest data block read, so the unread top data blocks
+  // cost no steps.
+  std::vector<int> by_degree;
+  for (int i = 0; i < m_; ++i) by_degree.push_back(k_ + i);
+  for (int j = 0; j < k_; ++j) by_degree.push_back(j);
+  const int want = (flags & RS_POLY_FLAG_ALL_SURVIVORS) ? n : k_;
   std::vector<int> unknown(e, e + t);  // erased first, in output order
-  for (int b = 0; b < n; ++b) {
+  for (int b : by_degree) {
     if (erased[b]) continue;
-    if (b < k_) {
+    if ((int)plan->read.size() < want)
       plan->read.push_back(b);
-    } else if (parity_needed > 0) {
-      plan->read.push_back(b);
-      --parity_needed;
-    } else {
+    else
       unknown.push_back(b);  // survivor left unread: solved for, discarded
-    }
   }
+  std::sort(plan->read.begin(), plan->read.end());
+  plan->span = 1;
+  for (int b : plan->read)
+    if (b < k_) plan->span = std::max(plan->span, b + 1);
   const int u = (int)unknown.size();
 
   // V[i][j] = alpha^(i pos(U_j)), i, j < u, over the unknown positions; the

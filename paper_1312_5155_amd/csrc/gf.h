@@ -47,6 +47,8 @@ struct Basis {
 // A decode plan: which blocks are read and the packed apply-table bases.
 struct DecodePlan {
   std::vector<int> read;          // API indices read, increasing
+  int span = 1;                   // 1 + highest data index read (at least 1):
+                                  // the LFSR starts at data block span - 1
   std::vector<uint8_t> coeffs;    // t x m, row e = rebuilt symbol e
   uint32_t apply_basis[kMaxM][16];
 };

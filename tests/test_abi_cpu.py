@@ -98,7 +98,7 @@ def test_validation_happens_before_any_device_call():
     holes[5] = None
     assert dec([5], blocks=holes) == B.RS_ENULL
     holes2 = (ctypes.c_void_p * 14)(*([0x1000] * 14))
-    holes2[13] = None       # parity p3, unread when only data block 2 is lost
+    holes2[9] = None        # data block 9, unread when only data block 2 is lost
     assert dec([2], blocks=holes2, nbytes=0) == B.RS_OK
     assert dec([2], blocks=holes2, flags=B.RS_POLY_FLAG_ALL_SURVIVORS, nbytes=0) == B.RS_ENULL
     d = (ctypes.c_void_p * 10)(*([0x1000] * 10))
@@ -150,6 +150,22 @@ def test_decode_plan_every_pattern_rs63(flags):
         assert len(read) == (k + m - len(er) if flags else k)
         for e, v in out.items():
             assert np.array_equal(v, full[e]), (er, e)
+
+
+def test_decode_reads_the_lowest_degree_survivors():
+    # Default read set: the k survivors of lowest degree (p_i at degree i,
+    # d_j at degree m + j), found here by brute force over the pattern.
+    for k, m in [(10, 4), (6, 3), (2, 4), (32, 8)]:
+        code = B.Code(k, m)
+        rng = workloads.meta_rng(77 + k)
+        for _ in range(30):
+            er = workloads.random_erasures(rng, k + m, int(rng.integers(1, m + 1)))
+            degree = {b: (b - k if b >= k else m + b) for b in range(k + m)}
+            surv = sorted((b for b in range(k + m) if b not in er), key=degree.get)
+            read, _ = code.decode_plan(er, 0)
+            assert read == sorted(surv[:k]), (k, m, er)
+            read_all, _ = code.decode_plan(er, B.RS_POLY_FLAG_ALL_SURVIVORS)
+            assert read_all == sorted(surv), (k, m, er)
 
 
 @pytest.mark.parametrize("k,m,w,poly", [(10, 4, 8, 0x11D), (12, 4, 8, 0x11D),
