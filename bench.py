@@ -255,6 +255,46 @@ def cpu_baseline(host_stripes, erasures, threads):
     return user / dt / 1e9, dt, parity
 
 
+def bitmatrix_compare(dev, stream, steps):
+    """Plain (one launch) encode of one RS(10,4) stripe of 64 MiB blocks:
+    the LFSR kernel against the bit-sliced XOR-only kernel, same buffers;
+    the two parities must be identical."""
+    import torch
+
+    from paper_1312_5155_amd import binding as B
+    nb = 64 << 20
+    code = B.Code(K, M)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(workloads.data_seed(3))
+    data = torch.randint(0, 256, (K, nb), dtype=torch.uint8, device=dev, generator=gen)
+    par = torch.zeros((2, M, nb), dtype=torch.uint8, device=dev)
+    dptr = [data[j].data_ptr() for j in range(K)]
+    runs = {"lfsr": lambda: B.rs_poly_encode(code.handle, dptr,
+                                             [par[0, i].data_ptr() for i in range(M)], nb, stream),
+            "bitmatrix": lambda: B.rs_poly_encode_bitmatrix(
+                code.handle, dptr, [par[1, i].data_ptr() for i in range(M)], nb, stream)}
+    out = {"workload": "RS(10,4) one stripe, 64 MiB blocks, plain launch",
+           "alg_bytes": (K + M) * nb}
+    for name, fn in runs.items():
+        for _ in range(5):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = median([a.elapsed_time(b) for a, b in ev])
+        out[name] = {"median_ms": round(ms, 4), "gbs": round((K + M) * nb / (ms / 1e3) / 1e9, 1)}
+    if not torch.equal(par[0], par[1]):
+        raise SystemExit("bit-matrix parity differs from the LFSR parity")
+    out["identical"] = True
+    del data, par
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -412,6 +452,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=30,
                     help="untimed steps first (the clocks settle over the first tens)")
     ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--bitmatrix-steps", type=int, default=20,
+                    help="timed launches of the plain LFSR and bit-matrix encodes of one "
+                         "RS(10,4) stripe of 64 MiB blocks (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=48,
                     help="stripes the CPU oracle encodes+decodes (0 = skip)")
     ap.add_argument("--update-steps", type=int, default=10,
@@ -569,6 +612,9 @@ def main():
                   "changed_blocks_per_stripe": 1}
         del delta
 
+    bitmatrix = bitmatrix_compare(dev, stream, args.bitmatrix_steps) \
+        if args.bitmatrix_steps > 0 else None
+
     # Self-consistency of the timed buffers (GPU path only): wiping stripe
     # 0's erased blocks and decoding again restores them.
     before = buf[0].clone()
@@ -648,6 +694,7 @@ def main():
                    "decode": batch.get_launch(B.RS_POLY_OP_DECODE, 0).as_dict(),
                    "update": batch.get_launch(B.RS_POLY_OP_UPDATE, 0).as_dict()},
         "plain": plain,
+        "bitmatrix": bitmatrix,
         "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -110,6 +110,25 @@ int rs_poly_generator(const rs_poly_t *h, uint8_t *g);
 int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data,
                    uint8_t *const *parity, size_t block_bytes, void *stream);
 
+/* Encode in bit-matrix (XOR-only) form, the multiplication-free direction
+ * that Sec. 6 proposes: the same parity bytes as rs_poly_encode, computed as
+ * parity p_i = sum_j c_ij d_j with c_ij the coefficient of x^i in
+ * x^(m+j) mod g(x) (the generator-matrix columns of Sec. 6), where each
+ * product by c_ij is an 8 x 8 matrix over GF(2) applied to the bit planes
+ * of the data bytes.  The XOR networks are fixed when the library is
+ * built, so only the codes that rs_poly_bitmatrix_supported accepts run.
+ *   data, parity, block_bytes  as rs_poly_encode; every pointer must be
+ *            16-byte aligned (any block_bytes)
+ * Errors: RS_ENULL (h, data, parity, or an entry), RS_EINVAL (code not
+ * built in, or a pointer not 16-byte aligned), RS_EDEVICE. */
+int rs_poly_encode_bitmatrix(rs_poly_t *h, const uint8_t *const *data,
+                             uint8_t *const *parity, size_t block_bytes, void *stream);
+
+/* 1 if rs_poly_encode_bitmatrix runs the code (k, m) over GF(2^w) with
+ * polynomial prim_poly, else 0: built in are RS(6,3), RS(10,4), RS(12,4)
+ * and RS(32,8) over GF(2^8) with polynomial 0x11D.  Host only. */
+int rs_poly_bitmatrix_supported(int k, int m, int w, unsigned prim_poly);
+
 /* Delta-parity update (the update property of Sec. 3.2): encoding is
  * linear, so when data blocks change, the parity of the new data is the old
  * parity plus the encoding of the data difference.  For every byte column c,

@@ -60,6 +60,8 @@ def load():
     lib.rs_poly_generator.argtypes = [vp, u8p]
     lib.rs_poly_encode.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_update.argtypes = [vp, pp, pp, sz, vp]
+    lib.rs_poly_encode_bitmatrix.argtypes = [vp, pp, pp, sz, vp]
+    lib.rs_poly_bitmatrix_supported.argtypes = [i, i, i, u]
     lib.rs_poly_decode.argtypes = [vp, pp, sz, ip, i, u, vp]
     lib.rs_poly_decode_plan.argtypes = [vp, ip, i, u, ip, ip, u8p]
     sp = ctypes.POINTER(Stripe)
@@ -212,6 +214,16 @@ def rs_poly_encode(h, data, parity, block_bytes, stream=None):
                  "rs_poly_encode")
 
 
+def rs_poly_encode_bitmatrix(h, data, parity, block_bytes, stream=None):
+    d, p = _ptr_array(data), _ptr_array(parity)
+    return check(load().rs_poly_encode_bitmatrix(h, d, p, block_bytes, _stream(stream)),
+                 "rs_poly_encode_bitmatrix")
+
+
+def rs_poly_bitmatrix_supported(k, m, w=8, prim_poly=0x11D):
+    return bool(load().rs_poly_bitmatrix_supported(k, m, w, prim_poly))
+
+
 def rs_poly_update(h, delta, parity, block_bytes, stream=None):
     d, p = _ptr_array(delta), _ptr_array(parity)
     return check(load().rs_poly_update(h, d, p, block_bytes, _stream(stream)),
@@ -346,6 +358,13 @@ class Code:
         if block_bytes is None:
             block_bytes = data[0].numel()
         return rs_poly_encode(self._h, list(data), list(parity), block_bytes, stream)
+
+    def encode_bitmatrix(self, data, parity, block_bytes=None, stream=None):
+        """The same parity as encode, from the bit-sliced XOR-only kernel
+        (codes for which rs_poly_bitmatrix_supported is true)."""
+        if block_bytes is None:
+            block_bytes = data[0].numel()
+        return rs_poly_encode_bitmatrix(self._h, list(data), list(parity), block_bytes, stream)
 
     def update(self, delta, parity, block_bytes=None, stream=None):
         """parity ^= encode(delta) in place; None entries of delta are

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librs_poly.so")
 
-SOURCES = ["codec.hip", "gf.cpp", "api.cpp", "batch.cpp", "serve.cpp"]
+SOURCES = ["codec.hip", "bitmatrix.hip", "gf.cpp", "api.cpp", "batch.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

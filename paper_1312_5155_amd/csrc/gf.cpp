@@ -15,6 +15,7 @@ bool Field::init(int w, unsigned poly) {
   const int q = 1 << w;
   if ((poly >> w) != 1u) return false;
   w_ = w;
+  poly_ = poly;
   order_ = q - 1;
   for (int i = 0; i < 256; ++i) log_[i] = -1;
   // Successive powers of alpha = x; a power seen twice before q-1 steps

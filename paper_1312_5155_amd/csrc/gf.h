@@ -32,9 +32,11 @@ class Field {
   }
   int order() const { return order_; }
   int w() const { return w_; }
+  unsigned poly() const { return poly_; }
 
  private:
   int w_ = 0, order_ = 0;
+  unsigned poly_ = 0;
   uint8_t exp_[512] = {};  // doubled so that exp_[log a + log b] needs no mod
   int log_[256] = {};
 };

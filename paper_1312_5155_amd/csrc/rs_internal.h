@@ -73,6 +73,15 @@ struct LaunchCfg {
 int launch_codec(Mode mode, int state_bytes, const CodecParams &p,
                  const LaunchCfg &cfg, void *stream);
 
+// Bit-sliced encode (bitmatrix.hip): compiled in for a few codes over
+// GF(2^8) with polynomial 0x11D; blocks 16-byte aligned.  launch_bitmatrix
+// encodes columns [offset, offset + block_bytes) (block_bytes <=
+// kMaxPieceBytes) and returns a hipError_t as int.
+constexpr int kBitmatrixMaxK = 32;
+bool bitmatrix_supported(int k, int m, int w, unsigned poly);
+int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *parity,
+                     uint64_t offset, uint64_t block_bytes, void *stream);
+
 // ------------------------------------------------------------- batches --
 //
 // A batch group holds stripes whose codes share a state width.  Its columns

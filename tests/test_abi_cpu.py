@@ -107,6 +107,20 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_encode(h, None, p, 16, None) == B.RS_ENULL
     p[2] = None
     assert lib.rs_poly_encode(h, d, p, 16, None) == B.RS_ENULL
+    # bit-matrix encode: built-in codes only, 16-byte aligned pointers
+    p3 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
+    enc_bm = lib.rs_poly_encode_bitmatrix
+    assert enc_bm(h, d, p3, 0, None) == B.RS_OK                    # empty: no-op
+    assert enc_bm(h, None, p3, 16, None) == B.RS_ENULL
+    assert enc_bm(None, d, p3, 16, None) == B.RS_ENULL
+    d_odd = (ctypes.c_void_p * 10)(*([0x1000] * 9 + [0x1008]))
+    assert enc_bm(h, d_odd, p3, 16, None) == B.RS_EINVAL            # 8-byte aligned
+    h93 = B.Code(9, 3)
+    assert enc_bm(h93.handle, d, p3, 16, None) == B.RS_EINVAL       # not built in
+    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x11D) == 1
+    assert lib.rs_poly_bitmatrix_supported(32, 8, 8, 0x11D) == 1
+    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x12B) == 0
+    assert lib.rs_poly_bitmatrix_supported(4, 3, 4, 0x13) == 0
     # update: NULL delta entries are unchanged blocks; parity is required
     nod = (ctypes.c_void_p * 10)()
     p2 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
