@@ -219,7 +219,8 @@ typedef struct rs_poly_launch {
                            * every workgroup gets work                         */
     int wgs_per_cu;       /* persistent workgroups per CU: 1 or 2              */
     int table_placement;  /* LFSR tables in LDS: RS_POLY_TABLES_PACKED or      *
-                           * RS_POLY_TABLES_NIBBLE                             */
+                           * RS_POLY_TABLES_NIBBLE; encode also                *
+                           * RS_POLY_TABLES_BITMATRIX                          */
     int tile_order;       /* 0: tiles handed out in order (the workgroups work *
                            * on neighbouring tiles); 1: each workgroup walks   *
                            * its own run of tiles (dynamic claims either way)  */
@@ -231,6 +232,12 @@ typedef struct rs_poly_launch {
  * from two 16-entry tables, two lookups per symbol and 1/8 of the LDS. */
 #define RS_POLY_TABLES_PACKED 0
 #define RS_POLY_TABLES_NIBBLE 1
+/* Encode only: no tables -- the bit-sliced XOR-only kernel of
+ * rs_poly_encode_bitmatrix, for a state width whose stripes in the call all
+ * use one code that rs_poly_bitmatrix_supported accepts (any other call runs
+ * the PACKED tables with the same launch shape).  Tiles are rounded down to
+ * a multiple of 2048 columns; bytes_per_lane does not apply. */
+#define RS_POLY_TABLES_BITMATRIX 2
 
 #define RS_POLY_OP_ENCODE 0
 #define RS_POLY_OP_DECODE 1

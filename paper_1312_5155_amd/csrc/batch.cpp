@@ -42,7 +42,9 @@ struct GroupBuf {
 
 // (op, width, bytes per lane, threads, WGs per CU, table placement, staging
 // buffer, buffer version)
-using GraphKey = std::tuple<int, int, int, int, int, int, int, uint64_t>;
+// (op, wide, bytes/lane, threads, wgs/CU, placement, staging, version,
+// bit-sliced code k * 256 + m or 0)
+using GraphKey = std::tuple<int, int, int, int, int, int, int, uint64_t, int>;
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
@@ -55,7 +57,8 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
   const Mode mode = op == RS_POLY_OP_DECODE ? kDecode : op == RS_POLY_OP_UPDATE ? kUpdate : kEncode;
   if (c.threads > codec_max_threads(mode, wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
   if (c.tile_bytes < 4096 || c.tile_bytes % 16 != 0) return false;
-  if (c.table_placement != RS_POLY_TABLES_PACKED && c.table_placement != RS_POLY_TABLES_NIBBLE)
+  if (c.table_placement != RS_POLY_TABLES_PACKED && c.table_placement != RS_POLY_TABLES_NIBBLE &&
+      !(c.table_placement == RS_POLY_TABLES_BITMATRIX && op == RS_POLY_OP_ENCODE))
     return false;
   if (c.tile_order != 0 && c.tile_order != 1) return false;
   return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 2;
@@ -123,7 +126,8 @@ struct rs_poly_batch {
   void drop_graphs_of(int wide);
   int ensure_staging(int i, const size_t *bytes);
   int ensure_group(int wide, size_t arena_bytes, uint64_t tiles, uint32_t stripes);
-  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, hipGraphExec_t *out);
+  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, int bm_k, int bm_m,
+                hipGraphExec_t *out);
   int run(int op, const rs_poly_stripe_t *stripes, int count, void *stream);
 };
 
@@ -226,11 +230,11 @@ int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
   return RS_OK;
 }
 
-int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si,
-                             hipGraphExec_t *out) {
+int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, int bm_k,
+                             int bm_m, hipGraphExec_t *out) {
   GroupBuf &gb = groups[wide];
   const GraphKey key{op,          wide, cfg.bytes_per_lane, cfg.threads, cfg.wgs_per_cu,
-                     cfg.table_placement, si, gb.version};
+                     cfg.table_placement, si, gb.version, bm_k * 256 + bm_m};
   auto it = graphs.find(key);
   if (it != graphs.end()) {
     *out = it->second.exec;
@@ -245,6 +249,8 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int 
   lc.grid = num_cu * cfg.wgs_per_cu;
   lc.bytewise = false;
   lc.nibble = cfg.table_placement == RS_POLY_TABLES_NIBBLE;
+  lc.bm_k = bm_k;
+  lc.bm_m = bm_m;
   GraphEntry e;
   if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return RS_EDEVICE;
@@ -290,6 +296,7 @@ struct GroupPlan {
   };
   std::map<MatrixKey, uint32_t> matrix_index;
   bool matrix = false;   // update group in the generator-matrix form
+  int bm_k = 0, bm_m = 0;  // encode group of one RS(bm_k, bm_m) code, bit-sliced
   std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
   uint64_t tiles = 0;
   uint32_t tile_cols = 0;
@@ -362,6 +369,33 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
       int which[kMatrixMaxBlocks];
       if (update_changed(st.code->code, st.blocks, which) > kMatrixMaxBlocks)
         plan[st.code->code.state_bytes() == 8].matrix = false;
+    }
+  }
+
+  // Encodes: a state width's stripes take the bit-sliced kernel when the
+  // launch asks for it and they all use one code built into that kernel;
+  // otherwise they run the packed LFSR tables.
+  if (op == RS_POLY_OP_ENCODE) {
+    for (int w = 0; w < kWidths; ++w) {
+      if (launch[op][w].table_placement != RS_POLY_TABLES_BITMATRIX) continue;
+      const Code *first = nullptr;
+      bool one_code = true;
+      for (int i = 0; i < count && one_code; ++i) {
+        if (!stripes[i].code) break;   // rejected below
+        const Code &c = stripes[i].code->code;
+        if ((c.state_bytes() == 8) != (w == 1)) continue;
+        if (!first)
+          first = &c;
+        else
+          one_code = c.k() == first->k() && c.m() == first->m() &&
+                     c.field().w() == first->field().w() &&
+                     c.field().poly() == first->field().poly();
+      }
+      if (one_code && first &&
+          bitmatrix_supported(first->k(), first->m(), first->field().w(), first->field().poly())) {
+        plan[w].bm_k = first->k();
+        plan[w].bm_m = first->m();
+      }
     }
   }
 
@@ -474,6 +508,8 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     const uint64_t want = cols / (2ull * num_cu * lc.wgs_per_cu);
     uint64_t tc = std::min<uint64_t>((uint64_t)lc.tile_bytes, std::max<uint64_t>(4096, want));
     tc = tc / 16 * 16;
+    // the bit-sliced kernel's waves take whole 2048-column chunks
+    if (gp.bm_k) tc = std::max<uint64_t>(kBitmatrixTileCols, tc / kBitmatrixTileCols * kBitmatrixTileCols);
     gp.tile_cols = (uint32_t)tc;
     uint64_t t = 0;
     for (auto &d : gp.descs) {
@@ -526,7 +562,8 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   for (int w = 0; w < kWidths; ++w) {
     if (plan[w].descs.empty()) continue;
     hipGraphExec_t exec;
-    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], si, &exec);
+    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], si, plan[w].bm_k,
+                   plan[w].bm_m, &exec);
     if (rc != RS_OK) return rc;
     if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
   }
@@ -718,8 +755,11 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
       for (int th : {256, 512, 1024})
         for (int tile : {8 << 10, 16 << 10, 64 << 10, 256 << 10})
           for (int wgs = 1; wgs <= 2; ++wgs)
-            for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE})
+            for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE, RS_POLY_TABLES_BITMATRIX})
               for (int order = 0; order <= 1; ++order) {
+                // (the bit-sliced kernel has one lane shape; the bytes per
+                // lane only matter for groups that fall back to tables)
+                if (tp == RS_POLY_TABLES_BITMATRIX && bpl != 16) continue;
                 const rs_poly_launch_t c{bpl, th, tile, wgs, tp, order};
                 if (valid_launch(op, w, c)) cands.push_back(c);
               }

@@ -179,34 +179,66 @@ struct BitmatrixParams {
   uint64_t block_bytes;
 };
 
-constexpr int kBitmatrixThreads = 256;
-constexpr uint64_t kWaveCols = 2048;   // 64 lanes x 32 columns
+constexpr uint64_t kWaveCols = kBitmatrixTileCols;   // 64 lanes x 32 columns
 
-// One wave encodes columns [c, c + 2048): lane l holds columns c + 16l ..
-// c + 16l + 15 (dwords 0-3) and c + 1024 + 16l .. (dwords 4-7).  Blocks
-// are loaded one ahead of the block being XORed in.  FULL: the 2048
-// columns lie inside the blocks (every wave but the last one of a launch).
-template <int K, int M, bool FULL>
-__device__ __forceinline__ void encode_columns(const BitmatrixParams &p, uint64_t s0,
-                                               uint64_t s1, uint64_t B) {
+// Block pointers of one stripe: kernel arguments (plain launch) or the
+// batch pointer table (k data, m parity-in, then the m parity outputs).
+struct ArgBlocks {
+  const BitmatrixParams &p;
+  __device__ const uint8_t *data(int j) const { return p.data[j]; }
+  __device__ uint8_t *parity(int i) const { return p.parity[i]; }
+};
+
+template <class T>
+using const_as = const __attribute__((address_space(4))) T *;
+
+template <int K, int M>
+struct TableBlocks {
+  const_as<uint64_t> ptrs;
+  __device__ const uint8_t *data(int j) const {
+    return reinterpret_cast<const uint8_t *>(ptrs[j]);
+  }
+  __device__ uint8_t *parity(int i) const { return reinterpret_cast<uint8_t *>(ptrs[K + M + i]); }
+};
+
+// Blocks loaded ahead of the one being XORed in: each lane keeps
+// kDepth + 1 blocks of 32 bytes in registers besides the m x 8 parity planes.
+template <int M>
+constexpr int bitmatrix_depth() { return M <= 4 ? 3 : 2; }
+
+// One wave encodes 2048 columns of a stripe: lane l holds columns s0 ..
+// s0 + 15 (dwords 0-3) and s1 = s0 + 1024 .. (dwords 4-7).  FULL: all of
+// them lie below `lim`; otherwise columns from `lim` on are neither read
+// nor written.
+template <int K, int M, bool FULL, class Blocks>
+__device__ __forceinline__ void encode_columns(const Blocks &src, uint64_t s0, uint64_t s1,
+                                               uint64_t lim) {
+  // (the byte-wise tail path loads one block ahead only)
+  constexpr int kD = FULL ? bitmatrix_depth<M>() : 1;
+  constexpr int D = kD < K ? kD : K;
+  constexpr int R = D + 1;
   uint32_t par[M][8];
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
     for (int b = 0; b < 8; ++b) par[i][b] = 0;
 
-  uint32_t cur[8], nxt[8];
-  load16<FULL>(p.data[0], s0, B, cur);
-  load16<FULL>(p.data[0], s1, B, cur + 4);
+  uint32_t blk[R][8];   // block j in blk[j % R]
+  unroll<D>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    load16<FULL>(src.data(j), s0, lim, blk[j]);
+    load16<FULL>(src.data(j), s1, lim, blk[j] + 4);
+  });
   unroll<K>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    if constexpr (j + 1 < K) {
-      load16<FULL>(p.data[j + 1], s0, B, nxt);
-      load16<FULL>(p.data[j + 1], s1, B, nxt + 4);
+    if constexpr (j + D < K) {
+      load16<FULL>(src.data(j + D), s0, lim, blk[(j + D) % R]);
+      load16<FULL>(src.data(j + D), s1, lim, blk[(j + D) % R] + 4);
     }
     // keep the scheduler from hoisting later blocks' loads above this
     // block's work (their registers would not fit)
     __builtin_amdgcn_sched_barrier(0);
+    uint32_t(&cur)[8] = blk[j % R];
     bit_transpose(cur);   // cur[b] = bit plane b of the lane's 32 columns
     unroll<M>([&](auto I) {
       constexpr int i = decltype(I)::value;
@@ -221,59 +253,122 @@ __device__ __forceinline__ void encode_columns(const BitmatrixParams &p, uint64_
         asm volatile("" : "+v"(par[i][b]));
       });
     });
-    if constexpr (j + 1 < K) {
-#pragma unroll
-      for (int d = 0; d < 8; ++d) cur[d] = nxt[d];
-    }
   });
 
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     bit_transpose(par[i]);
-    store16<FULL>(p.parity[i], s0, B, par[i]);
-    store16<FULL>(p.parity[i], s1, B, par[i] + 4);
+    store16<FULL>(src.parity(i), s0, lim, par[i]);
+    store16<FULL>(src.parity(i), s1, lim, par[i] + 4);
   }
 }
 
-// Register budget: M parity x 8 planes, two blocks of 8 dwords, temporaries.
+// Columns [c, min(c + 2048, lim)) by one wave.
+template <int K, int M, class Blocks>
+__device__ __forceinline__ void encode_chunk(const Blocks &src, uint64_t c, uint64_t lim,
+                                             uint32_t lane) {
+  const uint64_t s0 = c + 16 * lane, s1 = s0 + 1024;
+  if (c + kWaveCols <= lim)
+    encode_columns<K, M, true>(src, s0, s1, lim);
+  else
+    encode_columns<K, M, false>(src, s0, s1, lim);
+}
+
+// Register budget: M parity x 8 planes, kDepth + 1 blocks of 8 dwords,
+// temporaries.
 template <int M>
-constexpr int bitmatrix_waves_per_eu() { return M <= 4 ? 6 : 4; }
+constexpr int bitmatrix_waves_per_eu() { return M <= 4 ? 5 : 4; }
+
+constexpr int kBitmatrixThreads = 256;
 
 template <int K, int M>
 __global__ void __launch_bounds__(kBitmatrixThreads)
 __attribute__((amdgpu_waves_per_eu(bitmatrix_waves_per_eu<M>()))) bitmatrix_kernel(BitmatrixParams p) {
-  const uint64_t B = p.block_bytes;
-  const uint32_t lane = threadIdx.x & 63;
   const uint64_t wave = ((uint64_t)blockIdx.x * kBitmatrixThreads + threadIdx.x) >> 6;
   const uint64_t c = wave * kWaveCols;
-  if (c >= B) return;
-  const uint64_t s0 = c + 16 * lane, s1 = s0 + 1024;
-  if (c + kWaveCols <= B)
-    encode_columns<K, M, true>(p, s0, s1, B);
-  else
-    encode_columns<K, M, false>(p, s0, s1, B);
+  if (c >= p.block_bytes) return;
+  encode_chunk<K, M>(ArgBlocks{p}, c, p.block_bytes, threadIdx.x & 63);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+// Persistent batch kernel: the tile loop of the table-driven batch kernel
+// (same arena, tile map and claim counter; tile_cols a multiple of 2048),
+// with the bit-sliced encode in place of the LFSR: the waves of a
+// workgroup take neighbouring 2048-column chunks of the tile.  Every
+// stripe of the group is an RS(K, M) stripe.
+template <int K, int M>
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(bitmatrix_waves_per_eu<M>()))) bitmatrix_batch_kernel(BatchGroup g) {
+  __shared__ uint64_t next_claim;
+  BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
+  const const_as<BatchHeader> chdr = (const_as<BatchHeader>)(uintptr_t)hdr;
+  const uint64_t total = chdr->total_tiles;
+  const const_as<StripeDesc> descs =
+      (const_as<StripeDesc>)(uintptr_t)(g.arena + chdr->off_descs);
+  const const_as<uint64_t> ptr_table = (const_as<uint64_t>)(uintptr_t)(g.arena + chdr->off_ptrs);
+  const const_as<uint32_t> tile_stripe = (const_as<uint32_t>)(uintptr_t)g.tile_stripe;
+  unsigned long long *counter = reinterpret_cast<unsigned long long *>(&hdr->counter);
+  const uint32_t tile_cols = chdr->tile_cols;
+  const uint32_t lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6),
+                 waves = blockDim.x >> 6;
+
+  // claim c -> tile: in order (0) or runs of neighbouring tiles per
+  // workgroup (1), as in the table-driven batch kernel
+  const bool runs = chdr->tile_order != 0;
+  const uint64_t P = gridDim.x;
+  const uint64_t run = (total + P - 1) / P;
+  const uint64_t claims = runs ? run * P : total;
+  if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
+  __syncthreads();
+  for (;;) {
+    const uint64_t c =
+        (uint64_t)uniform((uint32_t)(next_claim >> 32)) << 32 | uniform((uint32_t)next_claim);
+    __syncthreads();   // every thread has read next_claim
+    if (c >= claims) break;
+    if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
+    const uint64_t tile = runs ? (c % P) * run + c / P : c;
+    if (tile < total) {
+      const uint32_t s = tile_stripe[tile];
+      const uint64_t bytes = descs[s].block_bytes;
+      const uint64_t c0 = (tile - descs[s].tile_begin) * tile_cols;
+      const uint64_t c1 = bytes - c0 > tile_cols ? c0 + tile_cols : bytes;
+      const TableBlocks<K, M> src{ptr_table + descs[s].ptr_off};
+      for (uint64_t cc = c0 + (uint64_t)wave * kWaveCols; cc < c1; cc += (uint64_t)waves * kWaveCols)
+        encode_chunk<K, M>(src, cc, c1, lane);
+    }
+    __syncthreads();   // next_claim is about to change
+  }
 }
 
 using BitmatrixFn = void (*)(BitmatrixParams);
+using BitmatrixBatchFn = void (*)(BatchGroup);
+
+struct BitmatrixKernels {
+  BitmatrixFn plain;
+  BitmatrixBatchFn batch;
+};
 
 // The codes compiled in (GF(2^8), polynomial 0x11D).
-BitmatrixFn pick_bitmatrix(int k, int m) {
-  if (k == 6 && m == 3) return bitmatrix_kernel<6, 3>;
-  if (k == 10 && m == 4) return bitmatrix_kernel<10, 4>;
-  if (k == 12 && m == 4) return bitmatrix_kernel<12, 4>;
-  if (k == 32 && m == 8) return bitmatrix_kernel<32, 8>;
-  return nullptr;
+BitmatrixKernels pick_bitmatrix(int k, int m) {
+  if (k == 6 && m == 3) return {bitmatrix_kernel<6, 3>, bitmatrix_batch_kernel<6, 3>};
+  if (k == 10 && m == 4) return {bitmatrix_kernel<10, 4>, bitmatrix_batch_kernel<10, 4>};
+  if (k == 12 && m == 4) return {bitmatrix_kernel<12, 4>, bitmatrix_batch_kernel<12, 4>};
+  if (k == 32 && m == 8) return {bitmatrix_kernel<32, 8>, bitmatrix_batch_kernel<32, 8>};
+  return {nullptr, nullptr};
 }
 
 }  // namespace
 
 bool bitmatrix_supported(int k, int m, int w, unsigned poly) {
-  return w == 8 && poly == kPoly && pick_bitmatrix(k, m) != nullptr;
+  return w == 8 && poly == kPoly && pick_bitmatrix(k, m).plain != nullptr;
 }
 
 int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *parity,
                      uint64_t offset, uint64_t block_bytes, void *stream) {
-  const BitmatrixFn fn = pick_bitmatrix(k, m);
+  const BitmatrixFn fn = pick_bitmatrix(k, m).plain;
   if (!fn || block_bytes == 0 || block_bytes > kMaxPieceBytes) return (int)hipErrorInvalidValue;
   BitmatrixParams p{};
   for (int j = 0; j < k; ++j) p.data[j] = data[j] + offset;
@@ -283,6 +378,15 @@ int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *p
   const uint64_t wgs = (waves + kBitmatrixThreads / 64 - 1) / (kBitmatrixThreads / 64);
   hipLaunchKernelGGL(fn, dim3((uint32_t)wgs), dim3(kBitmatrixThreads), 0,
                      (hipStream_t)stream, p);
+  return (int)hipGetLastError();
+}
+
+int launch_bitmatrix_batch(int k, int m, const BatchGroup &g, int grid, int threads,
+                           void *stream) {
+  const BitmatrixBatchFn fn = pick_bitmatrix(k, m).batch;
+  if (!fn || threads < 64 || threads > 1024 || threads % 64 || grid < 1)
+    return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, (hipStream_t)stream, g);
   return (int)hipGetLastError();
 }
 

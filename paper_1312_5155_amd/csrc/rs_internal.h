@@ -67,20 +67,16 @@ struct LaunchCfg {
   int grid;              // workgroups; 0 = pick from the size
   bool bytewise;         // byte loads/stores (for misaligned blocks)
   bool nibble;           // batch kernels: split-nibble LFSR tables
+  int bm_k = 0, bm_m = 0;  // batch encode: the bit-sliced kernel of RS(bm_k, bm_m)
 };
 
 // Launches the codec kernel for one stripe.  Returns a hipError_t as int.
 int launch_codec(Mode mode, int state_bytes, const CodecParams &p,
                  const LaunchCfg &cfg, void *stream);
 
-// Bit-sliced encode (bitmatrix.hip): compiled in for a few codes over
-// GF(2^8) with polynomial 0x11D; blocks 16-byte aligned.  launch_bitmatrix
-// encodes columns [offset, offset + block_bytes) (block_bytes <=
-// kMaxPieceBytes) and returns a hipError_t as int.
+// Largest k of the bit-sliced encode's codes; whether a code is built in.
 constexpr int kBitmatrixMaxK = 32;
 bool bitmatrix_supported(int k, int m, int w, unsigned poly);
-int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *parity,
-                     uint64_t offset, uint64_t block_bytes, void *stream);
 
 // ------------------------------------------------------------- batches --
 //
@@ -131,6 +127,19 @@ const uint8_t *device_zero_page();
 // int.
 int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint64_t max_tiles,
                  const LaunchCfg &cfg, void *stream);
+
+// Bit-sliced encode (bitmatrix.hip): compiled in for a few codes over
+// GF(2^8) with polynomial 0x11D; blocks 16-byte aligned.  launch_bitmatrix
+// encodes columns [offset, offset + block_bytes) (block_bytes <=
+// kMaxPieceBytes); launch_bitmatrix_batch launches the persistent batch
+// kernel for a group of RS(k, m) encode stripes whose tile_cols is a
+// multiple of kBitmatrixTileCols (after the pull and prepare kernels).
+// Both return a hipError_t as int.
+int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *parity,
+                     uint64_t offset, uint64_t block_bytes, void *stream);
+int launch_bitmatrix_batch(int k, int m, const BatchGroup &g, int grid, int threads,
+                           void *stream);
+constexpr uint32_t kBitmatrixTileCols = 2048;
 
 // Resident workgroups per CU the kernel is sized for (LDS bound).
 int codec_wgs_per_cu(Mode mode);

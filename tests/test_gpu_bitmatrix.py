@@ -94,3 +94,56 @@ def test_bitmatrix_full_size_agrees_with_lfsr_encode(k, m, Bn):
     for lo in (0, Bn // 2 - 1000, Bn - 3000):
         d = data[:, lo:lo + 3000].cpu().numpy()
         assert np.array_equal(p2[:, lo:lo + 3000].cpu().numpy(), oracle.encode(F, k, m, d))
+
+
+def batch_encode(stripes_np, codes, launch):
+    """Batched encode of the given stripes (one (k, B) array each) with the
+    launch shape `launch`; returns each stripe's parity."""
+    bufs, ents = [], []
+    for data, code in zip(stripes_np, codes):
+        k, Bn = data.shape
+        stride = (Bn + 255) // 256 * 256
+        t = torch.zeros((k + code.m) * stride, dtype=torch.uint8, device="cuda")
+        for j in range(k):
+            t[j * stride: j * stride + Bn] = torch.from_numpy(np.ascontiguousarray(data[j])).cuda()
+        t[k * stride:] = 0xA5
+        bufs.append((t, stride))
+        ents.append((code, [t.data_ptr() + b * stride for b in range(k + code.m)], Bn))
+    bt = B.Batch()
+    bt.set_launch(B.RS_POLY_OP_ENCODE, 1 if codes[0].m > 4 else 0, launch)
+    bt.encode(B.StripeArray(ents))
+    torch.cuda.synchronize()
+    out = []
+    for (t, stride), data, code in zip(bufs, stripes_np, codes):
+        k, Bn = data.shape
+        host = t.cpu().numpy()
+        out.append(np.stack([host[(k + i) * stride:(k + i) * stride + Bn] for i in range(code.m)]))
+    return out
+
+
+@pytest.mark.parametrize("k,m", [(10, 4), (32, 8), (6, 3)])
+@pytest.mark.parametrize("threads,tile,order", [(256, 8192, 0), (1024, 65536, 1), (512, 16384, 0)])
+def test_batched_bitmatrix_matches_oracle(k, m, threads, tile, order):
+    say(f"batched bit-matrix RS({k},{m}) threads={threads} tile={tile} order={order}")
+    F = oracle.Field(8, 0x11D)
+    sizes = [1, 4095, 2048, 70001, 1 << 16, 3 * 2048 + 17, 200000]
+    data = [workloads.random_bytes(77 * k + i, (k, n)) for i, n in enumerate(sizes)]
+    codes = [B.Code(k, m)] * len(sizes)
+    # (bytes_per_lane only shapes the table fallback; it must still be valid)
+    bpl = 4 if threads == 1024 else 16 if m <= 4 else 8
+    launch = {"bytes_per_lane": bpl, "threads": threads, "tile_bytes": tile,
+              "wgs_per_cu": 2, "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": order}
+    for par, d in zip(batch_encode(data, codes, launch), data):
+        assert np.array_equal(par, oracle.encode(F, k, m, d))
+
+
+def test_batched_bitmatrix_mixed_codes_fall_back_to_tables():
+    # Two codes in one width: the call runs the packed tables; same bytes.
+    F = oracle.Field(8, 0x11D)
+    specs = [(10, 4, 5000), (12, 4, 7000), (10, 4, 4096), (9, 4, 3000)]
+    data = [workloads.random_bytes(5 + i, (k, n)) for i, (k, _, n) in enumerate(specs)]
+    codes = [B.Code(k, m) for k, m, _ in specs]
+    launch = {"bytes_per_lane": 16, "threads": 512, "tile_bytes": 16384, "wgs_per_cu": 2,
+              "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0}
+    for par, d, (k, m, _) in zip(batch_encode(data, codes, launch), data, specs):
+        assert np.array_equal(par, oracle.encode(F, k, m, d))
