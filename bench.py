@@ -612,8 +612,33 @@ def main():
                   "changed_blocks_per_stripe": 1}
         del delta
 
-    bitmatrix = bitmatrix_compare(dev, stream, args.bitmatrix_steps) \
-        if args.bitmatrix_steps > 0 else None
+    bitmatrix = None
+    if args.bitmatrix_steps > 0:
+        bitmatrix = bitmatrix_compare(dev, stream, args.bitmatrix_steps)
+        # the batched encode above, again with the bit-sliced kernel
+        saved = batch.get_launch(B.RS_POLY_OP_ENCODE, 0).as_dict()
+        bm_launch = {"bytes_per_lane": 16, "threads": 512, "tile_bytes": 16384, "wgs_per_cu": 2,
+                     "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0}
+        batch.set_launch(B.RS_POLY_OP_ENCODE, 0, bm_launch)
+        ref = buf[:, K:].clone()
+        for _ in range(args.warmup):
+            batch.encode(enc, stream)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(stream)
+            batch.encode(enc, stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        bm_ms = median([a.elapsed_time(b) for a, b in ev])
+        if not torch.equal(buf[:, K:], ref):
+            raise SystemExit("batched bit-matrix parity differs from the LFSR parity")
+        del ref
+        batch.set_launch(B.RS_POLY_OP_ENCODE, 0, saved)
+        bitmatrix["batched"] = {"workload": "rs104_256x1MiB encode", "launch": bm_launch,
+                                "median_ms": round(bm_ms, 4),
+                                "gbs": round(enc_alg / (bm_ms / 1e3) / 1e9, 1),
+                                "lfsr_median_ms": round(median(enc_all), 4)}
 
     # Self-consistency of the timed buffers (GPU path only): wiping stripe
     # 0's erased blocks and decoding again restores them.
