@@ -71,7 +71,8 @@ def batch_variant(op, launch, m=4, matrix_update=False):
 
 CALIB_BYTES = 1 << 30       # size of the copy that calibrates the counters
 # bench.py arguments of the counter runs (timed steps only, no serving)
-PMC_BENCH_ARGS = "--steps 3 --warmup 1 --plain-steps 0 --cpu-sample 0 --serving-requests 0"
+PMC_BENCH_ARGS = ("--steps 3 --warmup 1 --plain-steps 0 --cpu-sample 0 --serving-requests 0 "
+                  "--bitmatrix-steps 0")
 
 
 def calibrate_copy():
@@ -261,6 +262,7 @@ def bitmatrix_compare(dev, stream, steps):
     the two parities must be identical."""
     import torch
 
+    import workloads
     from paper_1312_5155_amd import binding as B
     nb = 64 << 20
     code = B.Code(K, M)

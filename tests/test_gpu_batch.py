@@ -204,7 +204,7 @@ def test_set_launch_validation():
     bt = B.Batch()
     bad = [dict(bytes_per_lane=3, threads=256, tile_bytes=4096, wgs_per_cu=1),
            dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
-                table_placement=2),
+                table_placement=3),
            dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
                 tile_order=2),
            dict(bytes_per_lane=16, threads=300, tile_bytes=4096, wgs_per_cu=1),
@@ -216,6 +216,14 @@ def test_set_launch_validation():
     with pytest.raises(B.RsPolyError):
         bt.set_launch(B.RS_POLY_OP_DECODE, 0, dict(bytes_per_lane=16, threads=1024,
                                                   tile_bytes=4096, wgs_per_cu=2))
+    # the bit-sliced placement is an encode kernel only
+    bt.set_launch(B.RS_POLY_OP_ENCODE, 0, dict(bytes_per_lane=16, threads=512, tile_bytes=4096,
+                                              wgs_per_cu=2,
+                                              table_placement=B.RS_POLY_TABLES_BITMATRIX))
+    for op in (B.RS_POLY_OP_DECODE, B.RS_POLY_OP_UPDATE):
+        with pytest.raises(B.RsPolyError):
+            bt.set_launch(op, 0, dict(bytes_per_lane=16, threads=512, tile_bytes=4096,
+                                      wgs_per_cu=2, table_placement=B.RS_POLY_TABLES_BITMATRIX))
     with pytest.raises(B.RsPolyError):
         bt.set_launch(B.RS_POLY_OP_ENCODE, 1, dict(bytes_per_lane=16, threads=512,
                                                   tile_bytes=4096, wgs_per_cu=1))
