@@ -80,3 +80,34 @@ def test_decode_and_update_over_2GiB(stripe):
     stripe[2, :NB] ^= delta
     torch.cuda.synchronize()
     check_windows(stripe, list(range(K, K + M)))
+
+
+def test_bitmatrix_encode_over_2GiB():
+    # The bit-sliced encode splits blocks over 2 GiB the same way, plain and
+    # batched; both equal the LFSR encode, and windows match the oracle.
+    k, m = 6, 3
+    say(f"bit-matrix encode RS({k},{m}) blocks of {NB} bytes")
+    rows = torch.zeros((k + 3 * m, NBP), dtype=torch.uint8, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.data_seed(10))
+    for j in range(k):
+        rows[j, :NB] = torch.randint(0, 256, (NB,), dtype=torch.uint8, device="cuda",
+                                     generator=gen)
+    code = B.Code(k, m)
+    ptr = [rows[b].data_ptr() for b in range(k + 3 * m)]
+    code.encode(ptr[:k], ptr[k:k + m], NB)
+    code.encode_bitmatrix(ptr[:k], ptr[k + m:k + 2 * m], NB)
+    bt = B.Batch()
+    bt.set_launch(B.RS_POLY_OP_ENCODE, 0,
+                  {"bytes_per_lane": 16, "threads": 512, "tile_bytes": 16384, "wgs_per_cu": 2,
+                   "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0})
+    bt.encode([(code, ptr[:k] + ptr[k + 2 * m:], NB)])
+    torch.cuda.synchronize()
+    assert torch.equal(rows[k:k + m, :NB], rows[k + m:k + 2 * m, :NB])
+    assert torch.equal(rows[k:k + m, :NB], rows[k + 2 * m:, :NB])
+    F = oracle.Field(8, 0x11D)
+    for lo, hi in WINDOWS:
+        d = rows[:k, lo:hi].cpu().numpy()
+        assert np.array_equal(rows[k + m:k + 2 * m, lo:hi].cpu().numpy(), oracle.encode(F, k, m, d))
+    del rows
+    torch.cuda.empty_cache()
