@@ -41,9 +41,7 @@ struct GroupBuf {
 };
 
 // (op, width, bytes per lane, threads, WGs per CU, table placement, staging
-// buffer, buffer version)
-// (op, wide, bytes/lane, threads, wgs/CU, placement, staging, version,
-// bit-sliced code k * 256 + m or 0)
+// buffer, buffer version, bit-sliced code k * 256 + m or 0)
 using GraphKey = std::tuple<int, int, int, int, int, int, int, uint64_t, int>;
 
 struct GraphEntry {

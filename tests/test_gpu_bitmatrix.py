@@ -147,3 +147,36 @@ def test_batched_bitmatrix_mixed_codes_fall_back_to_tables():
               "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0}
     for par, d, (k, m, _) in zip(batch_encode(data, codes, launch), data, specs):
         assert np.array_equal(par, oracle.encode(F, k, m, d))
+
+
+def test_batched_bitmatrix_full_bench_workload():
+    # The bench's batched comparison run: 256 RS(10,4) stripes of 1 MiB blocks
+    # in the bench's bit-sliced launch shape; every parity byte equals the
+    # LFSR batch's, and sampled stripes match the oracle.
+    say("batched bit-matrix RS(10,4) 256 x 1 MiB")
+    k, m, S, nb = 10, 4, 256, 1 << 20
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.data_seed(1))
+    buf = torch.zeros((S, k + 2 * m, nb), dtype=torch.uint8, device="cuda")
+    buf[:, :k] = torch.randint(0, 256, (S, k, nb), dtype=torch.uint8, device="cuda",
+                               generator=gen)
+    code = B.Code(k, m)
+    lfsr = B.StripeArray([(code, [buf[s, b].data_ptr() for b in range(k + m)], nb)
+                          for s in range(S)])
+    bits = B.StripeArray([(code, [buf[s, b].data_ptr() for b in range(k)] +
+                           [buf[s, k + m + i].data_ptr() for i in range(m)], nb)
+                          for s in range(S)])
+    bt = B.Batch()
+    bt.encode(lfsr)
+    bt.set_launch(B.RS_POLY_OP_ENCODE, 0,
+                  {"bytes_per_lane": 16, "threads": 512, "tile_bytes": 16384, "wgs_per_cu": 2,
+                   "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0})
+    bt.encode(bits)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[:, k:k + m], buf[:, k + m:])
+    F = oracle.Field(8, 0x11D)
+    for s in (0, 97, 255):
+        d = buf[s, :k, :65536].cpu().numpy()
+        assert np.array_equal(buf[s, k + m:, :65536].cpu().numpy(), oracle.encode(F, k, m, d))
+    del buf
+    torch.cuda.empty_cache()
