@@ -619,7 +619,7 @@ def main():
         bitmatrix = bitmatrix_compare(dev, stream, args.bitmatrix_steps)
         # the batched encode above, again with the bit-sliced kernel
         saved = batch.get_launch(B.RS_POLY_OP_ENCODE, 0).as_dict()
-        bm_launch = {"bytes_per_lane": 16, "threads": 512, "tile_bytes": 16384, "wgs_per_cu": 2,
+        bm_launch = {"bytes_per_lane": 16, "threads": 256, "tile_bytes": 8192, "wgs_per_cu": 2,
                      "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0}
         batch.set_launch(B.RS_POLY_OP_ENCODE, 0, bm_launch)
         ref = buf[:, K:].clone()

@@ -169,7 +169,7 @@ def test_batched_bitmatrix_full_bench_workload():
     bt = B.Batch()
     bt.encode(lfsr)
     bt.set_launch(B.RS_POLY_OP_ENCODE, 0,
-                  {"bytes_per_lane": 16, "threads": 512, "tile_bytes": 16384, "wgs_per_cu": 2,
+                  {"bytes_per_lane": 16, "threads": 256, "tile_bytes": 8192, "wgs_per_cu": 2,
                    "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 0})
     bt.encode(bits)
     torch.cuda.synchronize()
