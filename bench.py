@@ -57,15 +57,18 @@ def measured_traffic(kernel, src_hash, variant):
     return entry.get("hbm_bytes_per_launch")
 
 
-def batch_variant(op, launch, m=4, matrix_update=False):
+def batch_variant(op, launch, m=4, matrix_update=False, k=10):
     """Name of the batch kernel template a launch shape runs (state width 4
     for m <= 4), as the profiler prints it.  An update of at most 8 changed
     blocks per stripe runs the generator-matrix form (mode 3), which has no
-    table-placement variants."""
+    table-placement variants; an encode with the bit-sliced placement runs
+    bitmatrix_batch_kernel<k, m> (the workloads that time it use one code)."""
     if op == 2 and matrix_update:
         mode = 3
+    elif op == 0 and launch["table_placement"] == 2:
+        return f"bitmatrix_batch_kernel<{k}, {m}>"
     else:
-        mode = op + (4 if launch["table_placement"] else 0)
+        mode = op + (4 if launch["table_placement"] == 1 else 0)
     return f"batch_kernel<{4 if m <= 4 else 8}, {launch['bytes_per_lane'] // 4}, {mode}>"
 
 

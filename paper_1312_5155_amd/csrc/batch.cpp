@@ -756,8 +756,9 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
             for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE, RS_POLY_TABLES_BITMATRIX})
               for (int order = 0; order <= 1; ++order) {
                 // (the bit-sliced kernel has one lane shape; the bytes per
-                // lane only matter for groups that fall back to tables)
-                if (tp == RS_POLY_TABLES_BITMATRIX && bpl != 16) continue;
+                // lane only shape the table fallback, and 4 is valid with
+                // every workgroup size)
+                if (tp == RS_POLY_TABLES_BITMATRIX && bpl != 4) continue;
                 const rs_poly_launch_t c{bpl, th, tile, wgs, tp, order};
                 if (valid_launch(op, w, c)) cands.push_back(c);
               }
