@@ -31,8 +31,10 @@
  * library owns the code handle and everything hung off it (tables, the
  * per-erasure-pattern coefficient cache, batch descriptors, graphs), released
  * by the matching *_free call.  Full speed needs 16-byte-aligned block
- * pointers and block sizes that are a multiple of 16; any alignment and size
- * is accepted, smaller alignments take slower load paths.
+ * pointers and block sizes that are a multiple of 16.  The one-stripe
+ * encode, decode and update accept any alignment and size (smaller
+ * alignments take slower load paths); the batch calls and the bit-sliced
+ * encode require 16-byte-aligned pointers (any size).
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the legacy
  * default stream).  Encode and decode are asynchronous: they enqueue work on
