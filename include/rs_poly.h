@@ -131,6 +131,19 @@ int rs_poly_encode_bitmatrix(rs_poly_t *h, const uint8_t *const *data,
  * and RS(32,8) over GF(2^8) with polynomial 0x11D.  Host only. */
 int rs_poly_bitmatrix_supported(int k, int m, int w, unsigned prim_poly);
 
+/* Encode in generator-matrix form (Sec. 6): the same parity bytes as
+ * rs_poly_encode, computed as p = sum_j P[:, j] d_j with column P[:, j] the
+ * remainder of x^(m+j) mod g(x), one packed table lookup per data block and
+ * column and no serial LFSR chain.  The tables of all k blocks share one LDS
+ * row, so the code must have k <= 8 (RS_POLY_MATRIX_MAX_K); it is the kernel
+ * of rs_poly_update's matrix form, updating zero parity by the data.
+ *   data, parity, block_bytes  as rs_poly_encode (any alignment)
+ * Errors: RS_ENULL (h, data, parity, or an entry), RS_EINVAL (k > 8),
+ * RS_EDEVICE. */
+#define RS_POLY_MATRIX_MAX_K 8
+int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data,
+                          uint8_t *const *parity, size_t block_bytes, void *stream);
+
 /* Delta-parity update (the update property of Sec. 3.2): encoding is
  * linear, so when data blocks change, the parity of the new data is the old
  * parity plus the encoding of the data difference.  For every byte column c,

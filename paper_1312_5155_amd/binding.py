@@ -21,6 +21,7 @@ RS_ENOMEM = -6
 RS_EBUSY = -7
 RS_POLY_FLAG_ALL_SURVIVORS = 1
 RS_POLY_MAX_M = 8
+RS_POLY_MATRIX_MAX_K = 8
 RS_POLY_MAX_N = 255
 
 _lib = None
@@ -61,6 +62,7 @@ def load():
     lib.rs_poly_encode.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_update.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_encode_bitmatrix.argtypes = [vp, pp, pp, sz, vp]
+    lib.rs_poly_encode_matrix.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_bitmatrix_supported.argtypes = [i, i, i, u]
     lib.rs_poly_decode.argtypes = [vp, pp, sz, ip, i, u, vp]
     lib.rs_poly_decode_plan.argtypes = [vp, ip, i, u, ip, ip, u8p]
@@ -221,6 +223,12 @@ def rs_poly_encode_bitmatrix(h, data, parity, block_bytes, stream=None):
                  "rs_poly_encode_bitmatrix")
 
 
+def rs_poly_encode_matrix(h, data, parity, block_bytes, stream=None):
+    d, p = _ptr_array(data), _ptr_array(parity)
+    return check(load().rs_poly_encode_matrix(h, d, p, block_bytes, _stream(stream)),
+                 "rs_poly_encode_matrix")
+
+
 def rs_poly_bitmatrix_supported(k, m, w=8, prim_poly=0x11D):
     return bool(load().rs_poly_bitmatrix_supported(k, m, w, prim_poly))
 
@@ -366,6 +374,13 @@ class Code:
         if block_bytes is None:
             block_bytes = data[0].numel()
         return rs_poly_encode_bitmatrix(self._h, list(data), list(parity), block_bytes, stream)
+
+    def encode_matrix(self, data, parity, block_bytes=None, stream=None):
+        """The same parity as encode, from the generator-matrix kernel
+        (codes with k <= 8)."""
+        if block_bytes is None:
+            block_bytes = data[0].numel()
+        return rs_poly_encode_matrix(self._h, list(data), list(parity), block_bytes, stream)
 
     def update(self, delta, parity, block_bytes=None, stream=None):
         """parity ^= encode(delta) in place; None entries of delta are

@@ -281,6 +281,45 @@ int rs_poly_encode_bitmatrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *
   return RS_OK;
 }
 
+int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *const *parity,
+                          size_t block_bytes, void *stream) {
+  if (!h || !data || !parity) return RS_ENULL;
+  const Code &c = h->code;
+  if (c.k() > kMatrixMaxBlocks) return RS_EINVAL;
+  int align = 16;
+  for (int j = 0; j < c.k(); ++j) {
+    if (!data[j]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(data[j]));
+  }
+  for (int i = 0; i < c.m(); ++i) {
+    if (!parity[i]) return RS_ENULL;
+    align = std::min(align, pointer_alignment(parity[i]));
+  }
+  if (block_bytes == 0) return RS_OK;
+  // The matrix-form update of every data block from zero parity: the same
+  // kernel, with the old-parity reads sent to the zero page.
+  int which[kMatrixMaxBlocks];
+  for (int j = 0; j < c.k(); ++j) which[j] = j;
+
+  std::lock_guard<std::mutex> lock(h->mu);
+  const int ncu = device_cu_count();
+  const uint8_t *zp = device_zero_page();
+  if (ncu <= 0 || !zp) return RS_EDEVICE;
+  const int sb = c.state_bytes();
+  for (uint64_t off = 0; off < block_bytes; off += kMaxPieceBytes) {
+    const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
+    CodecParams p;
+    memset(&p, 0, sizeof(p));
+    fill_matrix_update_params(c, data, parity, which, c.k(), off, piece, &p);
+    for (int i = 0; i < c.m(); ++i) p.par_in[i] = nullptr;
+    p.zero_page = zp;
+    const LaunchCfg cfg = default_cfg(kUpdateMatrix, sb, piece, align, ncu);
+    const int rc = hip_status(launch_codec(kUpdateMatrix, sb, p, cfg, stream));
+    if (rc != RS_OK) return rc;
+  }
+  return RS_OK;
+}
+
 int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta, uint8_t *const *parity,
                    size_t block_bytes, void *stream) {
   if (!h || !delta || !parity) return RS_ENULL;

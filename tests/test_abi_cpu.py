@@ -121,6 +121,16 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_bitmatrix_supported(32, 8, 8, 0x11D) == 1
     assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x12B) == 0
     assert lib.rs_poly_bitmatrix_supported(4, 3, 4, 0x13) == 0
+    # generator-matrix encode: k <= 8 only
+    enc_mx = lib.rs_poly_encode_matrix
+    h6 = B.Code(6, 3)
+    d6 = (ctypes.c_void_p * 6)(*([0x1000] * 6))
+    p6 = (ctypes.c_void_p * 3)(*([0x2000] * 3))
+    assert enc_mx(h6.handle, d6, p6, 0, None) == B.RS_OK            # empty: no-op
+    assert enc_mx(h6.handle, None, p6, 16, None) == B.RS_ENULL
+    p6[1] = None
+    assert enc_mx(h6.handle, d6, p6, 16, None) == B.RS_ENULL
+    assert enc_mx(h, d, p3, 16, None) == B.RS_EINVAL                 # k = 10 > 8
     # update: NULL delta entries are unchanged blocks; parity is required
     nod = (ctypes.c_void_p * 10)()
     p2 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
