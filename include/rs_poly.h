@@ -197,6 +197,28 @@ int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures,
                         unsigned flags, int *read_set, int *n_read,
                         uint8_t *coeffs);
 
+/* Measurement probe, not coding: streams `stripes` stripes of n_in input
+ * and n_out output blocks of block_bytes each, block b of stripe s at
+ * base + s * stripe_stride + b * block_stride (inputs b < n_in, outputs
+ * n_in .. n_in + n_out - 1), reading every input byte once and writing
+ * every output byte once (each output is the XOR of the inputs), with the
+ * codec kernels' 16-byte non-temporal accesses and walk over column tiles
+ * of tile_bytes, but no table lookups.  Its rate is the HBM bandwidth this
+ * part achieves for the read:write mix of an encode (n_in = k, n_out = m)
+ * or a decode (k, t): the achievable roof beside the nominal peak.
+ *   base        device pointer, 16-byte aligned; the caller owns the memory
+ *               (outputs are overwritten)
+ *   strides     multiples of 16; blocks and stripes must not overlap:
+ *               block_bytes <= block_stride, (n_in + n_out) * block_stride
+ *               <= stripe_stride
+ *   n_in        1..RS_POLY_MAX_N;  n_out 1..RS_POLY_MAX_M
+ *   block_bytes multiple of 16, at most 2^31
+ *   tile_bytes  columns per tile: a multiple of 16, >= 4096
+ * Asynchronous on `stream`.  Errors: RS_ENULL, RS_EINVAL, RS_EDEVICE. */
+int rs_poly_stream_probe(uint8_t *base, size_t stripe_stride, size_t block_stride,
+                         int stripes, int n_in, int n_out, size_t block_bytes,
+                         int tile_bytes, void *stream);
+
 /* ------------------------------------------------------------ batches --
  *
  * Many stripes -- uneven block sizes, different codes -- go through ONE
@@ -285,6 +307,13 @@ int rs_poly_batch_encode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
  * Errors: RS_ENULL, RS_EINVAL, RS_ERANGE, RS_ETOOMANY, RS_ENOMEM,
  * RS_EDEVICE. */
 int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
+                         int count, void *stream);
+
+/* The same two calls under op-first names (rs_poly_<op>_batch); they
+ * behave exactly as rs_poly_batch_encode and rs_poly_batch_decode. */
+int rs_poly_encode_batch(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
+                         int count, void *stream);
+int rs_poly_decode_batch(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
                          int count, void *stream);
 
 /* Delta-parity updates (as rs_poly_update) of every stripe, with one graph

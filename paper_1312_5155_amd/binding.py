@@ -66,6 +66,7 @@ def load():
     lib.rs_poly_bitmatrix_supported.argtypes = [i, i, i, u]
     lib.rs_poly_decode.argtypes = [vp, pp, sz, ip, i, u, vp]
     lib.rs_poly_decode_plan.argtypes = [vp, ip, i, u, ip, ip, u8p]
+    lib.rs_poly_stream_probe.argtypes = [vp, sz, sz, i, i, i, sz, i, vp]
     sp = ctypes.POINTER(Stripe)
     lp = ctypes.POINTER(Launch)
     lib.rs_poly_batch_create.argtypes = [ctypes.POINTER(vp)]
@@ -74,6 +75,8 @@ def load():
     lib.rs_poly_batch_encode.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_decode.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_update.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_encode_batch.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_decode_batch.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_reserve.argtypes = [vp, i, sz]
     lib.rs_poly_batch_get_launch.argtypes = [vp, i, i, lp]
     lib.rs_poly_batch_set_launch.argtypes = [vp, i, i, lp]
@@ -305,6 +308,25 @@ def rs_poly_batch_decode(b, stripes, stream=None):
     sa = _stripes(stripes)
     return check(load().rs_poly_batch_decode(b, sa.arr, sa.count, _stream(stream)),
                  "rs_poly_batch_decode")
+
+
+def rs_poly_encode_batch(b, stripes, stream=None):
+    sa = _stripes(stripes)
+    return check(load().rs_poly_encode_batch(b, sa.arr, sa.count, _stream(stream)),
+                 "rs_poly_encode_batch")
+
+
+def rs_poly_decode_batch(b, stripes, stream=None):
+    sa = _stripes(stripes)
+    return check(load().rs_poly_decode_batch(b, sa.arr, sa.count, _stream(stream)),
+                 "rs_poly_decode_batch")
+
+
+def rs_poly_stream_probe(base, stripe_stride, block_stride, stripes, n_in, n_out, block_bytes,
+                         tile_bytes=65536, stream=None):
+    return check(load().rs_poly_stream_probe(_ptr(base), stripe_stride, block_stride, stripes,
+                                             n_in, n_out, block_bytes, tile_bytes,
+                                             _stream(stream)), "rs_poly_stream_probe")
 
 
 def rs_poly_batch_update(b, stripes, stream=None):

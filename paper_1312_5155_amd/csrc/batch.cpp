@@ -689,6 +689,16 @@ int rs_poly_batch_decode(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, in
   return b->run(RS_POLY_OP_DECODE, stripes, count, stream);
 }
 
+int rs_poly_encode_batch(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, int count,
+                         void *stream) {
+  return rs_poly_batch_encode(b, stripes, count, stream);
+}
+
+int rs_poly_decode_batch(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, int count,
+                         void *stream) {
+  return rs_poly_batch_decode(b, stripes, count, stream);
+}
+
 int rs_poly_batch_update(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes, int count,
                          void *stream) {
   if (!b) return RS_ENULL;

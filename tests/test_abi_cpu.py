@@ -142,6 +142,41 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_update(h, nod, p, 16, None) == B.RS_ENULL   # p[2] is NULL
 
 
+def test_boundary_names_of_the_batch_calls():
+    # rs_poly_encode_batch / rs_poly_decode_batch are the batch calls under
+    # op-first names; they validate exactly as rs_poly_batch_encode/decode.
+    lib = B.load()
+    for name in ("rs_poly_encode_batch", "rs_poly_decode_batch"):
+        fn = getattr(lib, name)
+        assert fn(None, None, 0, None) == B.RS_ENULL          # no batch object
+
+
+def test_stream_probe_validates_before_any_device_call():
+    lib = B.load()
+    probe = lib.rs_poly_stream_probe
+    base = ctypes.c_void_p(0x100000)
+    MiB = 1 << 20
+    ok = dict(ss=14 * MiB, bs=MiB, st=4, ni=10, no=4, bb=MiB, tb=65536)
+
+    def call(base=base, **kw):
+        a = {**ok, **kw}
+        return probe(base, a["ss"], a["bs"], a["st"], a["ni"], a["no"], a["bb"], a["tb"], None)
+
+    assert call(base=None) == B.RS_ENULL
+    assert call(st=0) == B.RS_OK                             # nothing to stream
+    assert call(bb=0) == B.RS_OK
+    assert call(base=ctypes.c_void_p(0x100008)) == B.RS_EINVAL   # 8-byte aligned
+    assert call(ni=0) == B.RS_EINVAL
+    assert call(no=0) == B.RS_EINVAL
+    assert call(no=9) == B.RS_EINVAL
+    assert call(st=-1) == B.RS_EINVAL
+    assert call(bb=MiB + 16) == B.RS_EINVAL                   # block over its stride
+    assert call(bb=1000) == B.RS_EINVAL                       # not a multiple of 16
+    assert call(ss=13 * MiB) == B.RS_EINVAL                   # stripe holds 14 blocks
+    assert call(tb=2048) == B.RS_EINVAL
+    assert call(tb=65537) == B.RS_EINVAL
+
+
 def apply_plan_on_cpu(F, k, m, full, erasures, flags, code):
     """Rebuilds the erased rows of `full` with the library's plan: remainder
     of the received word (unread and erased rows zeroed) by the oracle, then

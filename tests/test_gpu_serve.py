@@ -43,6 +43,21 @@ def outputs_of(c, nbytes):
             _dev_bytes(c.out[r], nbytes) for r in range(c.n_out)]
 
 
+def _hip():
+    import ctypes
+    lib = ctypes.CDLL("libamdhip64.so.7")
+    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return lib
+
+
+def _dev_tensor(ptr, nbytes):
+    # a device copy of nbytes at ptr (device to device), as a torch tensor
+    out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    assert _hip().hipMemcpy(out.data_ptr(), ptr, nbytes, 3) == 0
+    return out
+
+
 def _dev_bytes(ptr, nbytes):
     # copy nbytes of device memory at ptr to a host numpy array; opening the
     # runtime by its soname reuses the copy already loaded in the process
@@ -72,11 +87,12 @@ def test_results_identical_alone_and_in_the_mix():
     srv.close()
 
     srv = B.Serve(8 << 30, streams=4, max_batch=16, auto_release=False)
-    times = np.linspace(0, 3000, len(entries))     # all within 3 ms: they overlap
+    times = np.linspace(0, 300, len(entries))      # all within 0.3 ms: they overlap
     srv.replay(entries, times)
     done = drain(srv, len(entries))
     st = srv.stats()
     assert st["batches"] < len(entries)             # requests really were batched
+    assert st["peak_inflight_batches"] >= 2         # and batches ran at the same time
     for c in done:
         i = c.user_tag
         assert c.status == 0
@@ -158,4 +174,63 @@ def test_bad_requests_are_rejected():
             srv.submit(bad)
         assert ei.value.code == err
     assert len(drain(srv, 1)) == 1
+    srv.close()
+
+
+def test_serving_config_at_full_size():
+    # The serving workload as the benchmark runs it: RS(10,4), requests of
+    # log-uniform 64 KiB - 64 MiB of data, 70% encodes / 30% degraded reads
+    # with 1-4 erasures on 24 resident sets, a 64 GiB budget, 4 streams,
+    # batches of up to 64.  Every completion is checked before it is
+    # released: a decode's outputs are the lost blocks themselves, an
+    # encode's outputs equal the resident parity and match the oracle on a
+    # seeded window of up to 64 KiB.
+    say("serve: full-size serving config")
+    cfg = workloads.CONFIGS["serving_rs104"]
+    k, m = cfg["k"], cfg["m"]
+    code = B.Code(k, m)
+    max_block = -(-cfg["max_request"] // k)
+    n_sets = 24
+    sets = ResidentSets(code, n_sets, max_block, seed=workloads.data_seed(cfg["index"]))
+    seed = workloads.meta_seed(cfg["index"]) + 50
+    trace, _ = workloads.serving_trace(seed, 400, k, m, cfg["min_request"],
+                                       cfg["max_request"], cfg["encode_frac"], None, n_sets)
+    assert max(r["block_bytes"] for r in trace) > (32 << 20) // k    # large requests too
+    srv = B.Serve(cfg["hbm_budget"], streams=4, max_batch=64, auto_release=False,
+                  max_block_bytes=max_block)
+    srv.replay(sets.entries(trace), np.zeros(len(trace)))
+    F = oracle.Field(8, 0x11D)
+    rng = workloads.meta_rng(seed + 1)
+    seen = set()
+    t0 = time.time()
+    while len(seen) < len(trace):
+        for c in srv.poll(64, timeout_us=20000):
+            i = c.user_tag
+            r = trace[i]
+            nb = r["block_bytes"]
+            assert c.status == 0 and i not in seen
+            seen.add(i)
+            res = sets.buf[r["set"]]
+            if r["op"] == B.RS_POLY_OP_ENCODE:
+                assert c.n_out == m
+                outs = [_dev_tensor(c.out[p], nb) for p in range(m)]
+                for p in range(m):
+                    assert c.out_index[p] == k + p
+                    assert torch.equal(outs[p], res[k + p, :nb]), (i, p)
+                w = min(nb, 64 << 10)
+                c0 = int(rng.integers(0, nb - w + 1))
+                want = oracle.encode(F, k, m, res[:k, c0:c0 + w].cpu().numpy())
+                got = np.stack([o[c0:c0 + w].cpu().numpy() for o in outs])
+                assert np.array_equal(got, want), i
+            else:
+                lost = sorted(r["erasures"])
+                assert c.n_out == len(lost)
+                for j, b in enumerate(lost):
+                    assert c.out_index[j] == b
+                    assert torch.equal(_dev_tensor(c.out[j], nb), res[b, :nb]), (i, b)
+            srv.release(c.ticket)
+        assert time.time() - t0 < 240, f"only {len(seen)} of {len(trace)} completed"
+    st = srv.stats()
+    assert st["completed"] == len(trace) and st["budget_in_use"] == 0
+    assert 0 < st["budget_peak"] <= cfg["hbm_budget"]
     srv.close()
