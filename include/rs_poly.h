@@ -246,11 +246,9 @@ typedef struct rs_poly_stripe {
 
 /* Launch shape of a batch kernel (what the autotuner chooses). */
 typedef struct rs_poly_launch {
-    int bytes_per_lane;   /* columns per lane per block: 4, 8 or 16 (decode of *
-                           * m > 4: 4 or 8)                                    */
-    int threads;          /* workgroup size: 256, 512 or 1024; at 16 bytes per *
-                           * lane at most 512 (m <= 4) or 256 (m > 4); decode  *
-                           * of m > 4 at 8 bytes per lane at most 512          */
+    int bytes_per_lane;   /* columns per lane per block: 4, 8 or 16            */
+    int threads;          /* workgroup size: 256, 512, 768 or 1024; codes with *
+                           * m <= 4 at 16 bytes per lane take at most 512      */
     int tile_bytes;       /* most columns per tile: a multiple of 16, >= 4096; *
                            * calls with few columns use smaller tiles so that  *
                            * every workgroup gets work                         */

@@ -51,7 +51,8 @@ struct GraphEntry {
 
 bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
   if (c.bytes_per_lane != 4 && c.bytes_per_lane != 8 && c.bytes_per_lane != 16) return false;
-  if (c.threads != 256 && c.threads != 512 && c.threads != 1024) return false;
+  if (c.threads != 256 && c.threads != 512 && c.threads != 768 && c.threads != 1024)
+    return false;
   const Mode mode = op == RS_POLY_OP_DECODE ? kDecode : op == RS_POLY_OP_UPDATE ? kUpdate : kEncode;
   if (c.threads > codec_max_threads(mode, wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
   if (c.tile_bytes < 4096 || c.tile_bytes % 16 != 0) return false;
@@ -67,10 +68,11 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
 rs_poly_launch_t default_launch(int op, int wide) {
   rs_poly_launch_t c;
   if (wide) {
-    // RS(32,8), 64 x 32 x 4 MiB stripes
-    c.bytes_per_lane = op == RS_POLY_OP_DECODE ? 4 : 8;
+    // RS(32,8), 64 x 32 x 16 MiB stripes: 16 bytes per lane and 1024
+    // threads (four waves per SIMD at 128 VGPRs) for every op
+    c.bytes_per_lane = 16;
     c.threads = 1024;
-    c.tile_bytes = op == RS_POLY_OP_DECODE ? 256 << 10 : 64 << 10;
+    c.tile_bytes = 64 << 10;
   } else {
     c.bytes_per_lane = 16;
     c.threads = 512;
@@ -81,9 +83,9 @@ rs_poly_launch_t default_launch(int op, int wide) {
   c.table_placement = RS_POLY_TABLES_PACKED;
   // RS(32,8) with 16 MiB blocks: the 40 blocks of a stripe sit 16 MiB apart,
   // and walking them at one column offset from every workgroup at once is
-  // 11% slower for encode and update than giving each workgroup its own run
-  // of tiles; for 1 MiB blocks the in-order walk is 5-14% faster.
-  c.tile_order = wide && op != RS_POLY_OP_DECODE ? 1 : 0;
+  // 8-9% slower for encode than giving each workgroup its own run of tiles
+  // (2% for decode); for 1 MiB blocks the in-order walk is 5-14% faster.
+  c.tile_order = wide ? 1 : 0;
   return c;
 }
 
@@ -760,7 +762,7 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
     // every valid launch shape and table placement
     std::vector<rs_poly_launch_t> cands;
     for (int bpl : {4, 8, 16})
-      for (int th : {256, 512, 1024})
+      for (int th : {256, 512, 768, 1024})
         for (int tile : {8 << 10, 16 << 10, 64 << 10, 256 << 10})
           for (int wgs = 1; wgs <= 2; ++wgs)
             for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE, RS_POLY_TABLES_BITMATRIX})

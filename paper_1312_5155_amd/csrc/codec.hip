@@ -58,7 +58,9 @@
 // is set by the bytes in flight per CU and by how local the concurrent
 // accesses are.  Each lane walks its column chunks as a software pipeline
 // that keeps the loads of the next M blocks in flight while the current M
-// are absorbed.
+// are absorbed.  The wide codes at 16 bytes per lane (16 columns, 8 blocks
+// per item) keep one item buffer, reloaded as soon as it has been XORed into
+// the states, so that 1024 threads fit (128 VGPRs).
 #include <hip/hip_runtime.h>
 
 #include "rs_internal.h"
@@ -74,6 +76,21 @@ constexpr bool nibble_of(int v) { return (v & kNibbleBit) != 0; }
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
   return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// An empty asm that takes and gives back two column states: code that
+// reads them cannot move above it, code that writes them cannot move below.
+template <int NQ>
+__device__ __forceinline__ void pin_pair(uint32_t (&x)[NQ], uint32_t (&y)[NQ]) {
+  if constexpr (NQ == 1)
+    asm volatile("" : "+v"(x[0]), "+v"(y[0]));
+  else
+    asm volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(y[0]), "+v"(y[1]));
+}
+
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 __device__ __forceinline__ uint32_t rotl32(uint32_t x, int s) {
@@ -570,11 +587,10 @@ __device__ __forceinline__ void matrix_lookups(uint32_t d0, uint32_t d1, uint32_
 // state is still zero, so the feedback is zero and a step changes nothing.
 // A matrix-update item adds its blocks' packed products instead.
 template <int M, int W, int MODE>
-__device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
-                                            bool data_item, int g, int skip, const uint8_t *lds,
-                                            const Lanes<M, MODE> &t) {
+__device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
+                                           bool data_item, int g, const uint8_t *lds,
+                                           const Lanes<M, MODE> &t) {
   constexpr int NQ = M / 4;
-  constexpr int NC = 4 * W;
   constexpr bool kMatrix = op_of(MODE) == kUpdateMatrix;
   const bool lfsr = data_item && !kMatrix;
 #pragma unroll
@@ -616,7 +632,15 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
       for (int h = 0; h < NQ; ++h) s[4 * w + x][h] ^= d[h][x];
     }
   }
-  if (lfsr) {
+}
+
+// The M LFSR steps of a data item (after absorb_xor), less the first `skip`.
+template <int M, int W, int MODE>
+__device__ __forceinline__ void absorb_steps(uint32_t (&s)[4 * W][M / 4], bool data_item,
+                                             int skip, const uint8_t *lds,
+                                             const Lanes<M, MODE> &t) {
+  constexpr int NC = 4 * W;
+  if (data_item && op_of(MODE) != kUpdateMatrix) {
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       if (q < skip) continue;
@@ -624,6 +648,14 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
       for (int c = 0; c < NC; ++c) lfsr_step<M, MODE>(s[c], lds, t, q);
     }
   }
+}
+
+template <int M, int W, int MODE>
+__device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
+                                            bool data_item, int g, int skip, const uint8_t *lds,
+                                            const Lanes<M, MODE> &t) {
+  absorb_xor<M, W, MODE>(s, a, data_item, g, lds, t);
+  absorb_steps<M, W, MODE>(s, data_item, skip, lds, t);
 }
 
 // M = 8: brings the column states back from the lane's rotation phase
@@ -655,27 +687,57 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
   constexpr int NC = 4 * W;
   const int m = src.m(), n_out = src.n_out();
   if constexpr (op_of(MODE) == kDecode) {
-    // Column by column (few live registers): every lane walks all M tables
-    // (those past m are zero) in its rotated order.
+    // Column by column: every lane walks all M tables (those past m are
+    // zero) in its rotated order, and the M products are summed three at a
+    // time (v_bitop3_b32).  Two columns at a time: an empty asm that takes
+    // and gives back the states of a pair of columns before and after their
+    // lookups keeps the pairs in order; left free, the compiler issues the
+    // lookups of every column at once and holds all their results
+    // (8 columns x 8 products x 2 dwords).
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      uint32_t L[NQ];   // packed rebuilt symbols
-#pragma unroll
-      for (int h = 0; h < NQ; ++h) L[h] = 0;
+      if constexpr (NC > 1) {
+        if ((c & 1) == 0) pin_pair(s[c], s[c + 1]);
+      }
+      uint32_t v[M][NQ];
 #pragma unroll
       for (int b = 0; b < M; ++b) {
         if constexpr (M == 4) {
           const uint32_t addr = perm(s[c][0], t.aoff[b], t.asel[b]);
-          L[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
+          v[b][0] = *reinterpret_cast<const uint32_t *>(lds + addr);
         } else {
-          const uint32_t addr = perm(s[c][1], s[c][0], t.asel[b]) | t.aoff[b];
-          const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
-          L[0] ^= v.x;
-          L[1] ^= v.y;
+          // The apply tables sit 64 KiB above the LFSR copies at the same
+          // per-lane offsets (same rotation phase and replica), so the
+          // address is the LFSR one plus the region base in one v_or3_b32
+          // (the base in an SGPR keeps it out of the per-lane registers).
+          static_assert(Layout<M, MODE>::kApplyBase == 65536 &&
+                            Layout<M, MODE>::kTableBytes == Layout<M, MODE>::kCopyBytes,
+                        "apply offsets equal the LFSR offsets plus the base");
+          const uint32_t p = perm(s[c][1], s[c][0], t.lsel[b]);
+          uint32_t addr;
+          asm("v_or3_b32 %0, %1, %2, %3"
+              : "=v"(addr)
+              : "v"(p), "v"(t.loff[b]), "s"(Layout<M, MODE>::kApplyBase));
+          const uint2 x = *reinterpret_cast<const uint2 *>(lds + addr);
+          v[b][0] = x.x;
+          v[b][1] = x.y;
         }
       }
 #pragma unroll
-      for (int h = 0; h < NQ; ++h) s[c][h] = L[h];
+      for (int h = 0; h < NQ; ++h) {
+        uint32_t L = xor3(v[0][h], v[1][h], v[2][h]);
+        if constexpr (M == 4) {
+          L ^= v[3][h];
+        } else {
+          L = xor3(L, v[3][h], v[4][h]);
+          L = xor3(L, v[5][h], v[6][h]);
+          L ^= v[7][h];
+        }
+        s[c][h] = L;
+      }
+      if constexpr (NC > 1) {
+        if (c & 1) pin_pair(s[c - 1], s[c]);
+      }
     }
   }
 #pragma unroll
@@ -699,6 +761,14 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
         store_cols<W, BYTEWISE>(src.out(oi), col, src.B(), o[bb]);
     }
   }
+}
+
+// Whether a variant keeps one item buffer instead of two (see
+// process_columns): the wide codes at 16 bytes per lane, and the wide
+// decode at 8, which then fit four waves per SIMD (at most 128 VGPRs).
+template <int M, int W, int MODE>
+constexpr bool kSingleBuffer() {
+  return M == 8 && (W == 4 || (W == 2 && op_of(MODE) == kDecode));
 }
 
 // Encodes, updates or decodes chunks c0 + (r*lanes + lane)*NC, r = 0, 1,
@@ -742,6 +812,38 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
   uint32_t r = 0;   // round of the current item (uniform)
   int g = 0;        // item within the chunk (uniform)
   load_item<M, W, MODE, BYTEWISE>(src, col_of(0), 0, groups, false, a);
+
+  if constexpr (kSingleBuffer<M, W, MODE>()) {
+    // One item buffer: the item is XORed into the states first, then the
+    // next item's loads are issued into the same registers and stay in
+    // flight while the current one runs its LFSR steps.
+    for (;;) {
+      uint32_t nr = r;
+      int ng = g + 1;
+      if (ng == items) {
+        ng = 0;
+        ++nr;
+      }
+      const bool more = nr < rounds;
+      absorb_xor<M, W, MODE>(s, a, g < groups, g, lds, t);
+      // (keeps the next loads after the XOR, so they reuse the registers)
+      __builtin_amdgcn_sched_barrier(0);
+      load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, !more,
+                                      a);
+      absorb_steps<M, W, MODE>(s, g < groups, g == 0 ? lead : 0, lds, t);
+      if (g == groups - 1) unrotate<M, W, MODE>(s, t);
+      if (g == items - 1) {
+        finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, t);
+#pragma unroll
+        for (int c = 0; c < 4 * W; ++c)
+#pragma unroll
+          for (int h = 0; h < M / 4; ++h) s[c][h] = 0;
+      }
+      r = nr;
+      g = ng;
+      if (!more) return;
+    }
+  }
 
   // One pipeline stage: prefetch the item after (r, g) into nxt, consume cur.
   auto stage = [&](uint32_t (&cur)[M][W], uint32_t (&nxt)[M][W]) -> bool {
@@ -789,14 +891,13 @@ __device__ __forceinline__ void process_range(const Src &src, uint32_t c0, uint3
     process_columns<M, 1, MODE, true>(src, tail, (c1 - tail + 3) / 4, 0, 1, lds, t);
 }
 
-// Workgroup size bound per variant: the 16-byte-per-lane variants hold two
-// items of loads in flight and need more than 128 VGPRs, and so does the
-// wide decode at 8 bytes per lane (its lane constants cover 8 rotations and
-// 8 apply tables).  The wide decode has no 16-byte variant.
+// Workgroup size bound per variant: at most 128 VGPRs (four waves per SIMD)
+// for 1024 threads.  The narrow codes at 16 bytes per lane hold two items
+// of loads in flight and need more, so they take at most 512 threads; the
+// wide codes at 16 bytes per lane fit with one item buffer.
 template <int M, int W, int MODE>
 constexpr int max_threads() {
-  if (M == 8 && op_of(MODE) == kDecode) return W == 4 ? 0 : W == 2 ? 512 : 1024;
-  return W == 4 ? (M == 8 ? 256 : 512) : 1024;
+  return W == 4 && M == 4 ? 512 : 1024;
 }
 
 // One stripe per launch: grid-stride loop over its column chunks.
@@ -965,9 +1066,7 @@ BatchFn pick_batch(int sb, int w) {
     if (w == 2) return batch_kernel<4, 2, MODE>;
     return batch_kernel<4, 1, MODE>;
   }
-  if constexpr (op_of(MODE) != kDecode) {
-    if (w == 4) return batch_kernel<8, 4, MODE>;
-  }
+  if (w == 4) return batch_kernel<8, 4, MODE>;
   if (w >= 2) return batch_kernel<8, 2, MODE>;
   return batch_kernel<8, 1, MODE>;
 }
@@ -979,10 +1078,7 @@ int codec_wgs_per_cu(Mode) { return 2; }
 int codec_plain_max_dwords(int sb) { return sb == 8 ? 2 : 4; }
 
 int codec_max_threads(Mode mode, int sb, int dwords_per_lane) {
-  if (sb == 8 && mode == kDecode)
-    return dwords_per_lane == 4 ? 0 : dwords_per_lane == 2 ? 512 : 1024;
-  if (dwords_per_lane == 4) return sb == 8 ? 256 : 512;
-  return 1024;
+  return dwords_per_lane == 4 && sb == 4 ? 512 : 1024;
 }
 
 int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, void *stream) {

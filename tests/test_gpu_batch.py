@@ -166,7 +166,7 @@ def test_graph_replays_with_new_descriptors():
 
 
 @pytest.mark.parametrize("bpl", [4, 8, 16])
-@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("threads", [256, 768, 1024])
 @pytest.mark.parametrize("placement", [B.RS_POLY_TABLES_PACKED, B.RS_POLY_TABLES_NIBBLE])
 @pytest.mark.parametrize("order", [0, 1])
 def test_every_launch_shape(bpl, threads, placement, order):
@@ -176,15 +176,12 @@ def test_every_launch_shape(bpl, threads, placement, order):
     host = fill_data(arena, 21)
     bt = B.Batch()
     for wide in (0, 1):
-        # register-bound workgroup limits of the 16-byte-per-lane variants
-        th = min(threads, (256 if wide else 512) if bpl == 16 else 1024)
+        # register-bound workgroup limit of the narrow 16-byte-per-lane variants
+        th = min(threads, 512) if bpl == 16 and not wide else threads
         cfg = dict(bytes_per_lane=bpl, threads=th, tile_bytes=4096 * (1 + wide),
                    wgs_per_cu=1 + wide, table_placement=placement, tile_order=order)
         bt.set_launch(B.RS_POLY_OP_ENCODE, wide, cfg)
-        # the wide decode: at most 8 bytes per lane, 512 threads at 8
-        dbpl = min(bpl, 8) if wide else bpl
-        dth = min(th, 512) if wide and dbpl == 8 else th
-        bt.set_launch(B.RS_POLY_OP_DECODE, wide, dict(cfg, bytes_per_lane=dbpl, threads=dth))
+        bt.set_launch(B.RS_POLY_OP_DECODE, wide, cfg)
     bt.encode(encode_entries(arena))
     torch.cuda.synchronize()
     check_encoded(arena, host)
@@ -224,18 +221,19 @@ def test_set_launch_validation():
         with pytest.raises(B.RsPolyError):
             bt.set_launch(op, 0, dict(bytes_per_lane=16, threads=512, tile_bytes=4096,
                                       wgs_per_cu=2, table_placement=B.RS_POLY_TABLES_BITMATRIX))
+    # narrow codes at 16 bytes per lane take at most 512 threads; wide codes
+    # (m > 4) run every width with up to 1024, 768 included
     with pytest.raises(B.RsPolyError):
-        bt.set_launch(B.RS_POLY_OP_ENCODE, 1, dict(bytes_per_lane=16, threads=512,
+        bt.set_launch(B.RS_POLY_OP_ENCODE, 0, dict(bytes_per_lane=16, threads=1024,
                                                   tile_bytes=4096, wgs_per_cu=1))
-    bt.set_launch(B.RS_POLY_OP_ENCODE, 1, dict(bytes_per_lane=8, threads=1024,
-                                              tile_bytes=4096, wgs_per_cu=2))
-    # the wide decode has no 16-byte variant and runs 8 bytes with <= 512
-    for bad_wide in (dict(bytes_per_lane=16, threads=256, tile_bytes=4096, wgs_per_cu=1),
-                     dict(bytes_per_lane=8, threads=1024, tile_bytes=4096, wgs_per_cu=1)):
-        with pytest.raises(B.RsPolyError):
-            bt.set_launch(B.RS_POLY_OP_DECODE, 1, bad_wide)
-    bt.set_launch(B.RS_POLY_OP_DECODE, 1, dict(bytes_per_lane=8, threads=512,
-                                              tile_bytes=4096, wgs_per_cu=2))
+    for op in (B.RS_POLY_OP_ENCODE, B.RS_POLY_OP_DECODE, B.RS_POLY_OP_UPDATE):
+        for bpl in (4, 8, 16):
+            for th in (256, 512, 768, 1024):
+                bt.set_launch(op, 1, dict(bytes_per_lane=bpl, threads=th, tile_bytes=4096,
+                                          wgs_per_cu=1))
+    with pytest.raises(B.RsPolyError):
+        bt.set_launch(B.RS_POLY_OP_DECODE, 1, dict(bytes_per_lane=8, threads=640,
+                                                  tile_bytes=4096, wgs_per_cu=1))
 
 
 def test_batch_rejects_bad_input_without_running():
