@@ -19,6 +19,7 @@
 #include "gf.h"
 #include "rs_internal.h"
 #include "runtime.h"
+#include "batch_plan.h"
 
 namespace rsp {
 namespace {
@@ -44,6 +45,22 @@ struct GroupBuf {
 // buffer, buffer version, bit-sliced code k * 256 + m or 0)
 using GraphKey = std::tuple<int, int, int, int, int, int, int, uint64_t, int>;
 
+// Graphs are captured on one stream per device, shared by every batch
+// object (no work ever runs on it: a captured launch is only recorded), so
+// that batch objects add no stream of their own to the device's hardware
+// queues.  Created on first use (with the device current) and kept until the
+// process ends; captures hold g_capture_mu.
+std::mutex g_capture_mu;
+hipStream_t g_capture[64] = {};
+
+hipStream_t capture_stream(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  if (!g_capture[dev] &&
+      hipStreamCreateWithFlags(&g_capture[dev], hipStreamNonBlocking) != hipSuccess)
+    g_capture[dev] = nullptr;
+  return g_capture[dev];
+}
+
 struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -62,6 +79,8 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
   if (c.tile_order != 0 && c.tile_order != 1) return false;
   return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 2;
 }
+
+}  // namespace
 
 // Defaults from sweeps of every shape on RS(10,4), 256 x 1 MiB stripes (and
 // RS(32,8) for wide codes), MI355X; the autotuner refines them per workload.
@@ -89,7 +108,6 @@ rs_poly_launch_t default_launch(int op, int wide) {
   return c;
 }
 
-}  // namespace
 }  // namespace rsp
 
 using namespace rsp;
@@ -99,7 +117,6 @@ struct rs_poly_batch {
   int device = 0;
   int num_cu = 0;
   std::string arch;
-  hipStream_t capture = nullptr;
   GroupBuf groups[kWidths];
   // Two coherent pinned staging buffers per width, used in turn.  The pull
   // kernel of the call's graph reads them; each event marks the end of the
@@ -172,7 +189,6 @@ rs_poly_batch::~rs_poly_batch() {
   for (void *p : retired_dev) (void)hipFree(p);
   for (void *p : retired_host) (void)hipHostFree(p);
   if (last_done) (void)hipEventDestroy(last_done);
-  if (capture) (void)hipStreamDestroy(capture);
 }
 
 // Makes staging buffer pair i hold at least bytes[w] for each width and be
@@ -252,14 +268,21 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int 
   lc.bm_k = bm_k;
   lc.bm_m = bm_m;
   GraphEntry e;
-  if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
-    return RS_EDEVICE;
   const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
                     : op == RS_POLY_OP_UPDATE ? kUpdate
                     : op == kOpUpdateMatrix   ? kUpdateMatrix
                                               : kEncode;
-  const int lerr = launch_batch(mode, wide ? 8 : 4, g, gb.tile_cap, lc, capture);
-  const hipError_t cerr = hipStreamEndCapture(capture, &e.graph);
+  int lerr = 0;
+  hipError_t cerr = hipSuccess;
+  {
+    std::lock_guard<std::mutex> lock(g_capture_mu);
+    hipStream_t capture = capture_stream(device);
+    if (!capture) return RS_EDEVICE;
+    if (hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return RS_EDEVICE;
+    lerr = launch_batch(mode, wide ? 8 : 4, g, gb.tile_cap, lc, capture);
+    cerr = hipStreamEndCapture(capture, &e.graph);
+  }
   if (lerr != 0 || cerr != hipSuccess) {
     if (e.graph) (void)hipGraphDestroy(e.graph);
     return RS_EDEVICE;
@@ -273,48 +296,8 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int 
   return RS_OK;
 }
 
+
 namespace rsp {
-namespace {
-
-// Per-call host view of one group before upload.
-struct GroupPlan {
-  std::vector<StripeDesc> descs;
-  std::vector<uint64_t> ptrs;
-  std::vector<uint32_t> lfsr;   // 16 per set
-  std::vector<uint32_t> apply;  // kMaxM*16 per set
-  std::unordered_map<const Code *, uint32_t> lfsr_index;
-  std::unordered_map<const DecodePlan *, uint32_t> apply_index;
-  // matrix-form update: table bases per (code, changed-block set); the set
-  // is packed one index per byte (at most 8 indices below 255, count apart)
-  struct MatrixKey {
-    const Code *code;
-    uint64_t packed;
-    int n;
-    bool operator<(const MatrixKey &o) const {
-      return std::tie(code, packed, n) < std::tie(o.code, o.packed, o.n);
-    }
-  };
-  std::map<MatrixKey, uint32_t> matrix_index;
-  bool matrix = false;   // update group in the generator-matrix form
-  int bm_k = 0, bm_m = 0;  // encode group of one RS(bm_k, bm_m) code, bit-sliced
-  std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
-  uint64_t tiles = 0;
-  uint32_t tile_cols = 0;
-  uint64_t bytes = 0;   // user bytes (k * B summed), for tuning choices
-
-  size_t layout(size_t *o_descs, size_t *o_ptrs, size_t *o_lfsr, size_t *o_apply) const {
-    size_t off = align_up(sizeof(BatchHeader), 256);
-    *o_descs = off;
-    off = align_up(off + descs.size() * sizeof(StripeDesc), 256);
-    *o_ptrs = off;
-    off = align_up(off + ptrs.size() * sizeof(uint64_t), 256);
-    *o_lfsr = off;
-    off = align_up(off + lfsr.size() * sizeof(uint32_t), 256);
-    *o_apply = off;
-    off = align_up(off + apply.size() * sizeof(uint32_t), 256);
-    return off;
-  }
-};
 
 int check_stripe(int op, const rs_poly_stripe_t &st, int *sorted,
                  std::shared_ptr<const DecodePlan> *plan) {
@@ -352,13 +335,11 @@ int check_stripe(int op, const rs_poly_stripe_t &st, int *sorted,
   return RS_OK;
 }
 
-}  // namespace
-}  // namespace rsp
-
-int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void *stream) {
+int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
+               const rs_poly_launch_t *launch, int num_cu, GroupPlan *plan,
+               size_t *upload_len, size_t (*offs)[4], size_t *total_upload_out) {
   if (count < 0) return RS_EINVAL;
   if (count > 0 && !stripes) return RS_ENULL;
-  GroupPlan plan[kWidths];
   // Updates: a state width's stripes take the generator-matrix form when
   // none of them changes more than kMatrixMaxBlocks blocks.
   if (op == RS_POLY_OP_UPDATE) {
@@ -377,7 +358,7 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   // otherwise they run the packed LFSR tables.
   if (op == RS_POLY_OP_ENCODE) {
     for (int w = 0; w < kWidths; ++w) {
-      if (launch[op][w].table_placement != RS_POLY_TABLES_BITMATRIX) continue;
+      if (launch[w].table_placement != RS_POLY_TABLES_BITMATRIX) continue;
       const Code *first = nullptr;
       bool one_code = true;
       for (int i = 0; i < count && one_code; ++i) {
@@ -495,14 +476,12 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
 
   // Tiles per stripe depend on the launch shape of the group.
   size_t total_upload = 0;
-  size_t upload_len[kWidths] = {0, 0};
-  size_t offs[kWidths][4];
   for (int w = 0; w < kWidths; ++w) {
     GroupPlan &gp = plan[w];
     if (gp.descs.empty()) continue;
     // Tiles of at most the configured size, smaller when the batch is
     // small, so that every persistent workgroup gets about two tiles.
-    const rs_poly_launch_t &lc = launch[op][w];
+    const rs_poly_launch_t &lc = launch[w];
     uint64_t cols = 0;
     for (auto &d : gp.descs) cols += d.block_bytes;
     const uint64_t want = cols / (2ull * num_cu * lc.wgs_per_cu);
@@ -520,6 +499,40 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
     upload_len[w] = gp.layout(&offs[w][0], &offs[w][1], &offs[w][2], &offs[w][3]);
     total_upload += upload_len[w];
   }
+  *total_upload_out = total_upload;
+  return RS_OK;
+}
+
+void pack_group(const GroupPlan &gp, size_t upload_len, const size_t *offs, uint32_t tile_order,
+                uint8_t *h) {
+  BatchHeader hdr{};
+  hdr.upload_bytes = upload_len;
+  hdr.total_tiles = gp.tiles;
+  hdr.n_stripes = (uint32_t)gp.descs.size();
+  hdr.tile_cols = gp.tile_cols;
+  hdr.tile_order = tile_order;
+  hdr.off_descs = offs[0];
+  hdr.off_ptrs = offs[1];
+  hdr.off_lfsr = offs[2];
+  hdr.off_apply = offs[3];
+  memcpy(h, &hdr, sizeof(hdr));
+  memcpy(h + offs[0], gp.descs.data(), gp.descs.size() * sizeof(StripeDesc));
+  memcpy(h + offs[1], gp.ptrs.data(), gp.ptrs.size() * sizeof(uint64_t));
+  memcpy(h + offs[2], gp.lfsr.data(), gp.lfsr.size() * sizeof(uint32_t));
+  if (!gp.apply.empty())
+    memcpy(h + offs[3], gp.apply.data(), gp.apply.size() * sizeof(uint32_t));
+}
+
+}  // namespace rsp
+
+int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void *stream) {
+  GroupPlan plan[kWidths];
+  size_t upload_len[kWidths] = {0, 0};
+  size_t offs[kWidths][4];
+  size_t total_upload = 0;
+  const int prc = plan_batch(op, stripes, count, launch[op], num_cu, plan, upload_len, offs,
+                             &total_upload);
+  if (prc != RS_OK) return prc;
   if (total_upload == 0) return RS_OK;
 
   // Device buffers and pinned staging.
@@ -537,23 +550,7 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   for (int w = 0; w < kWidths; ++w) {
     GroupPlan &gp = plan[w];
     if (gp.descs.empty()) continue;
-    uint8_t *h = staging[w][si];
-    BatchHeader hdr{};
-    hdr.upload_bytes = upload_len[w];
-    hdr.total_tiles = gp.tiles;
-    hdr.n_stripes = (uint32_t)gp.descs.size();
-    hdr.tile_cols = gp.tile_cols;
-    hdr.tile_order = (uint32_t)launch[op][w].tile_order;
-    hdr.off_descs = offs[w][0];
-    hdr.off_ptrs = offs[w][1];
-    hdr.off_lfsr = offs[w][2];
-    hdr.off_apply = offs[w][3];
-    memcpy(h, &hdr, sizeof(hdr));
-    memcpy(h + offs[w][0], gp.descs.data(), gp.descs.size() * sizeof(StripeDesc));
-    memcpy(h + offs[w][1], gp.ptrs.data(), gp.ptrs.size() * sizeof(uint64_t));
-    memcpy(h + offs[w][2], gp.lfsr.data(), gp.lfsr.size() * sizeof(uint32_t));
-    if (!gp.apply.empty())
-      memcpy(h + offs[w][3], gp.apply.data(), gp.apply.size() * sizeof(uint32_t));
+    pack_group(gp, upload_len[w], offs[w], (uint32_t)launch[op][w].tile_order, staging[w][si]);
   }
   // The arena may still be read by the previous call's kernels if that call
   // went to another stream.
@@ -660,7 +657,6 @@ int rs_poly_batch_create(rs_poly_batch_t **out) {
   hipDeviceProp_t prop;
   if (hipGetDevice(&b->device) != hipSuccess ||
       hipGetDeviceProperties(&prop, b->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->staging_free[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->staging_free[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->last_done, hipEventDisableTiming) != hipSuccess) {

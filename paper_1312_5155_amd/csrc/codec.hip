@@ -831,7 +831,7 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
       load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, !more,
                                       a);
       absorb_steps<M, W, MODE>(s, g < groups, g == 0 ? lead : 0, lds, t);
-      if (g == groups - 1) unrotate<M, W, MODE>(s, t);
+      if (op_of(MODE) != kUpdateMatrix && g == groups - 1) unrotate<M, W, MODE>(s, t);
       if (g == items - 1) {
         finish_chunk<M, W, MODE, BYTEWISE>(src, col_of(r), r * lanes + lane < n, s, lds, t);
 #pragma unroll
@@ -1097,11 +1097,13 @@ int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, 
 }
 
 int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
-                 const LaunchCfg &cfg, void *stream) {
+                 const LaunchCfg &cfg, void *stream, bool pull) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(batch_pull_kernel, dim3(64), dim3(256), 0, st, g);
-  int perr = (int)hipGetLastError();
-  if (perr) return perr;
+  if (pull) {
+    hipLaunchKernelGGL(batch_pull_kernel, dim3(64), dim3(256), 0, st, g);
+    const int perr = (int)hipGetLastError();
+    if (perr) return perr;
+  }
   const uint32_t prep_threads = 256;
   const uint32_t prep_grid = (uint32_t)((max_tiles + prep_threads - 1) / prep_threads);
   hipLaunchKernelGGL(batch_prepare_kernel, dim3(prep_grid ? prep_grid : 1), dim3(prep_threads),

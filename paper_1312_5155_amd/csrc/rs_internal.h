@@ -122,11 +122,11 @@ struct BatchGroup {            // device pointers
 const uint8_t *device_zero_page();
 
 // Enqueues, for a group: the pull kernel (copies the upload from host_src to
-// the arena), the prepare kernel and the persistent batch kernel.  max_tiles
-// (the tile-map capacity) sizes the prepare grid.  Returns a hipError_t as
-// int.
+// the arena; left out when pull is false, the arena then already holding
+// it), the prepare kernel and the persistent batch kernel.  max_tiles (the
+// tile-map capacity) sizes the prepare grid.  Returns a hipError_t as int.
 int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint64_t max_tiles,
-                 const LaunchCfg &cfg, void *stream);
+                 const LaunchCfg &cfg, void *stream, bool pull = true);
 
 // Bit-sliced encode (bitmatrix.hip): compiled in for a few codes over
 // GF(2^8) with polynomial 0x11D; blocks 16-byte aligned.  launch_bitmatrix

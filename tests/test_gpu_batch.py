@@ -182,6 +182,7 @@ def test_every_launch_shape(bpl, threads, placement, order):
                    wgs_per_cu=1 + wide, table_placement=placement, tile_order=order)
         bt.set_launch(B.RS_POLY_OP_ENCODE, wide, cfg)
         bt.set_launch(B.RS_POLY_OP_DECODE, wide, cfg)
+        bt.set_launch(B.RS_POLY_OP_UPDATE, wide, cfg)
     bt.encode(encode_entries(arena))
     torch.cuda.synchronize()
     check_encoded(arena, host)
@@ -195,6 +196,28 @@ def test_every_launch_shape(bpl, threads, placement, order):
     bt.decode(entries)
     torch.cuda.synchronize()
     assert torch.equal(arena.buf, before)
+    # delta-parity update in both forms: two changed blocks (generator-matrix
+    # form) and every data block (LFSR form for k > 8); the delta of block j
+    # is block j itself, so the parity becomes old ^ encode(changed blocks)
+    for every in (False, True):
+        old = [[arena.block(s, k + i).cpu().numpy() for i in range(m)]
+               for s, (k, m, nbytes) in enumerate(shapes)]
+        ents, changed = [], []
+        for s, (k, m, nbytes) in enumerate(shapes):
+            ch = list(range(k)) if every else sorted({0, k - 1})
+            ptrs = arena.ptrs(s)
+            ents.append((code(k, m), [ptrs[j] if j in ch else None for j in range(k)] + ptrs[k:],
+                         nbytes))
+            changed.append(ch)
+        bt.update(ents)
+        torch.cuda.synchronize()
+        for s, (k, m, nbytes) in enumerate(shapes):
+            dd = np.zeros_like(host[s])
+            dd[changed[s]] = host[s][changed[s]]
+            want = oracle.encode(field(), k, m, dd)
+            for i in range(m):
+                got = arena.block(s, k + i).cpu().numpy()
+                assert np.array_equal(got, old[s][i] ^ want[i]), (every, s, i)
 
 
 def test_set_launch_validation():
