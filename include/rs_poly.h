@@ -323,6 +323,35 @@ int rs_poly_decode_batch(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
 int rs_poly_batch_update(rs_poly_batch_t *b, const rs_poly_stripe_t *stripes,
                          int count, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the batch calls with no
+ * batch object.  rs_poly_batch_noalloc(op, ...) does what
+ * rs_poly_batch_encode / _decode / _update do for op = RS_POLY_OP_ENCODE /
+ * _DECODE / _UPDATE -- same validation, same kernels, same bytes -- at the
+ * library's default launch shapes, but allocates no device memory, no
+ * pinned host memory and no stream, event or graph: its zero page,
+ * descriptor arena, tile map and tile counter live in one file-scope device
+ * array of RS_POLY_NOALLOC_SCRATCH_BYTES per GPU, held until the process
+ * ends (its address is looked up, and the array cleared, on the first call
+ * on each device, which synchronizes `stream` once).  The descriptors reach
+ * the array by an ordinary host-to-device copy on `stream` from library
+ * memory (host-side planning uses the C++ heap, as every call does).
+ * Limits, per state width (codes with m <= 4, and with 4 < m <= 8) of a
+ * call: the packed descriptors of its stripes (about 0.2-0.7 KiB per stripe,
+ * more for large k) must fit RS_POLY_NOALLOC_ARENA_BYTES and its tiles (of
+ * 8-64 KiB of columns each) RS_POLY_NOALLOC_MAX_TILES; larger calls are
+ * rejected with RS_EINVAL before any work.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on the device (queued on different
+ * streams without ordering between them) race and give undefined results;
+ * calls on one stream are ordered.
+ * Errors: as the batch calls, plus RS_EINVAL (op, or the limits above). */
+#define RS_POLY_NOALLOC_ARENA_BYTES (512u << 10)
+#define RS_POLY_NOALLOC_MAX_TILES (128u << 10)
+#define RS_POLY_NOALLOC_SCRATCH_BYTES \
+    ((64u << 10) + 2u * RS_POLY_NOALLOC_ARENA_BYTES + 2u * 4u * RS_POLY_NOALLOC_MAX_TILES)
+int rs_poly_batch_noalloc(int op, const rs_poly_stripe_t *stripes, int count,
+                          void *stream);
+
 /* Pre-sizes the object's device descriptor buffers, tile map and pinned
  * staging for calls of up to max_stripes stripes of up to max_block_bytes
  * each (any codes), so such calls never allocate.  Larger calls still work:

@@ -76,6 +76,7 @@ def load():
     lib.rs_poly_batch_decode.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_update.argtypes = [vp, sp, i, vp]
     lib.rs_poly_encode_batch.argtypes = [vp, sp, i, vp]
+    lib.rs_poly_batch_noalloc.argtypes = [i, sp, i, vp]
     lib.rs_poly_decode_batch.argtypes = [vp, sp, i, vp]
     lib.rs_poly_batch_reserve.argtypes = [vp, i, sz]
     lib.rs_poly_batch_get_launch.argtypes = [vp, i, i, lp]
@@ -320,6 +321,12 @@ def rs_poly_decode_batch(b, stripes, stream=None):
     sa = _stripes(stripes)
     return check(load().rs_poly_decode_batch(b, sa.arr, sa.count, _stream(stream)),
                  "rs_poly_decode_batch")
+
+
+def rs_poly_batch_noalloc(op, stripes, stream=None):
+    sa = _stripes(stripes)
+    return check(load().rs_poly_batch_noalloc(op, sa.arr, sa.count, _stream(stream)),
+                 "rs_poly_batch_noalloc")
 
 
 def rs_poly_stream_probe(base, stripe_stride, block_stride, stripes, n_in, n_out, block_bytes,

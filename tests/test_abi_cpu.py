@@ -151,6 +151,19 @@ def test_boundary_names_of_the_batch_calls():
         assert fn(None, None, 0, None) == B.RS_ENULL          # no batch object
 
 
+def test_noalloc_batch_validates_before_any_device_call():
+    lib = B.load()
+    code = B.Code(10, 4)
+    one = B.StripeArray([(code, [0x1000] * 14, 4096)])
+    assert lib.rs_poly_batch_noalloc(7, one.arr, 1, None) == B.RS_EINVAL     # unknown op
+    assert lib.rs_poly_batch_noalloc(-1, one.arr, 1, None) == B.RS_EINVAL
+    assert lib.rs_poly_batch_noalloc(B.RS_POLY_OP_ENCODE, one.arr, -1, None) == B.RS_EINVAL
+    assert lib.rs_poly_batch_noalloc(B.RS_POLY_OP_DECODE, None, 2, None) == B.RS_ENULL
+    assert lib.rs_poly_batch_noalloc(B.RS_POLY_OP_UPDATE, None, 0, None) == B.RS_OK
+    # the advertised scratch size is the sum of its regions
+    assert (64 << 10) + 2 * (512 << 10) + 2 * 4 * (128 << 10) == 2162688
+
+
 def test_stream_probe_validates_before_any_device_call():
     lib = B.load()
     probe = lib.rs_poly_stream_probe
