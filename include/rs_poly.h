@@ -402,7 +402,8 @@ typedef struct rs_serve_config {
                                * also the size of the output pool (> 0)       */
     int streams;              /* batches in flight at once, 1..8              */
     int max_batch;            /* most requests per batch, >= 1                */
-    int auto_release;         /* 1: free outputs and budget at completion     */
+    int auto_release;         /* 1: free outputs and budget at completion     *
+                               * (completions then carry no output pointers) */
     size_t max_block_bytes;   /* largest block_bytes accepted (0 = any); the  *
                                * batch buffers are reserved for it up front   */
 } rs_serve_config_t;
@@ -428,7 +429,9 @@ typedef struct rs_serve_completion {
     int n_out;                /* m (encode) or t (decode)                    */
     uint8_t *out[RS_POLY_MAX_M]; /* encode: p_0..p_(m-1); decode: blocks in   *
                                * increasing erased index order; owned by the  *
-                               * engine until released                       */
+                               * engine until released.  NULL with            *
+                               * auto_release (the outputs were freed when    *
+                               * the request completed)                       */
     int out_index[RS_POLY_MAX_M]; /* API index of each output block          */
     size_t charge_bytes;      /* budget held: (k+m)B encode, (k+t)B decode    */
     double queue_us;          /* submit -> batch launch                       */

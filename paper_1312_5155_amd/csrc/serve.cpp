@@ -46,8 +46,11 @@ class DevicePool {
   ~DevicePool() {
     if (base_) (void)hipFree(base_);
   }
-  // Returns the offset, or SIZE_MAX if the ring has no room now.
-  size_t alloc(size_t bytes) {
+  // Returns the offset, or SIZE_MAX if the ring has no room now; *slot
+  // receives the block's bookkeeping entry, which release() takes back
+  // (entries never move: the deque only grows at the back and shrinks at
+  // the front, which keeps references to the other entries valid).
+  size_t alloc(size_t bytes, void **slot) {
     bytes = (bytes + 255) / 256 * 256;
     if (bytes > size_) return SIZE_MAX;
     size_t off;
@@ -70,15 +73,13 @@ class DevicePool {
     }
     head_ = off + bytes;
     live_.push_back({off, bytes, false});
+    *slot = &live_.back();
     return off;
   }
-  void release(size_t off, size_t bytes) {
-    (void)bytes;
-    for (auto it = live_.begin(); it != live_.end(); ++it)
-      if (it->off == off && !it->freed) {
-        it->freed = true;
-        break;
-      }
+  // Marks the block of `slot` free and advances the tail over the freed
+  // blocks at the front: O(1) amortized.
+  void release(void *slot) {
+    static_cast<Block *>(slot)->freed = true;
     while (!live_.empty() && live_.front().freed) live_.pop_front();
     if (!live_.empty()) tail_ = live_.front().off;
   }
@@ -103,13 +104,13 @@ struct Request {
   size_t charge = 0;
   size_t out_bytes = 0;              // pool bytes of the outputs
   size_t out_off = SIZE_MAX;
+  void *out_slot = nullptr;          // the pool's entry for the outputs
   int n_out = 0;
   int status = RS_OK;
   Clock::time_point submitted, launched, done;
 };
 
 struct Slot {
-  uint64_t seq = 0;             // launch order of the batch it holds
   hipStream_t stream = nullptr;
   hipEvent_t start = nullptr;   // timing: before the batch's first command
   hipEvent_t done = nullptr;
@@ -141,7 +142,6 @@ struct rs_serve {
   rs_serve_stats_t stats{};
   bool stopping = false;
   int inflight = 0;
-  uint64_t launch_seq = 0;
   std::thread scheduler;
   std::vector<std::thread> replayers;
 
@@ -214,8 +214,9 @@ int rs_serve::enqueue(const rs_serve_request_t &r, uint64_t *ticket) {
 }
 
 void rs_serve::free_outputs(Request *q) {
-  if (q->out_off != SIZE_MAX) pool.release(q->out_off, q->out_bytes);
+  if (q->out_off != SIZE_MAX) pool.release(q->out_slot);
   q->out_off = SIZE_MAX;
+  q->out_slot = nullptr;
   in_use -= q->charge;
 }
 
@@ -254,9 +255,11 @@ void rs_serve::admit() {
   while (!pending.empty()) {
     Request *q = pending.front();
     if (in_use + q->charge > cfg.hbm_budget_bytes) break;
-    const size_t off = pool.alloc(q->out_bytes);
+    void *slot = nullptr;
+    const size_t off = pool.alloc(q->out_bytes, &slot);
     if (off == SIZE_MAX) break;
     q->out_off = off;
+    q->out_slot = slot;
     in_use += q->charge;
     stats.budget_peak = std::max(stats.budget_peak, in_use);
     pending.pop_front();
@@ -322,7 +325,6 @@ bool rs_serve::launch() {
   }
   slot->reqs = std::move(batch);
   slot->busy = true;
-  slot->seq = ++launch_seq;
   std::lock_guard<std::mutex> lock(mu);
   stats.launch_host_us += us_between(now, Clock::now());
   ++inflight;
@@ -344,11 +346,10 @@ void rs_serve::run() {
     admit();
     const Clock::time_point t1 = Clock::now();
     while (launch()) progress = true;
-    bool all_busy = true;
-    Slot *oldest = nullptr;
+    bool all_busy = true, any_busy = false;
     for (Slot &sl : slots) {
-      if (!sl.busy) all_busy = false;
-      else if (!oldest || sl.seq < oldest->seq) oldest = &sl;
+      all_busy = all_busy && sl.busy;
+      any_busy = any_busy || sl.busy;
     }
     bool work_waiting;
     {
@@ -357,21 +358,23 @@ void rs_serve::run() {
       const bool idle = pending.empty() && admitted.empty() && inflight == 0;
       if (stopping && idle) break;
       work_waiting = !pending.empty() || !admitted.empty();
-      if (!progress && !oldest) {
+      if (!progress && !any_busy) {
         // Nothing in flight: sleep until a submission arrives.
         cv_work.wait_for(lock, std::chrono::milliseconds(5));
         continue;
       }
     }
-    if (!progress && oldest && (all_busy || work_waiting)) {
+    if (!progress && (all_busy || work_waiting)) {
       // Every slot is busy, or admission waits for budget: nothing can
-      // happen before the oldest batch finishes, so block on it.
-      (void)hipEventSynchronize(oldest->done);
-    } else if (!progress && oldest) {
-      // Slots free, nothing queued: wake on a submission or poll the
-      // running batches soon.
-      std::unique_lock<std::mutex> lock(mu);
-      cv_work.wait_for(lock, std::chrono::microseconds(50));
+      // happen before some batch finishes.  Poll every busy slot (reap()
+      // queries each one's event) rather than blocking on one of them, so
+      // that whichever batch finishes first is seen, and stamped, when it
+      // finishes.
+      std::this_thread::yield();
+    } else if (!progress) {
+      // Slots free, nothing queued, batches in flight: keep polling them;
+      // a submission is picked up on the next pass.
+      std::this_thread::yield();
     }
   }
 }
