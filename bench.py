@@ -270,25 +270,30 @@ def time_batched(batch, enc, dec, stream, steps, warmup):
     return wall * 1e3 / steps, enc_all, dec_all
 
 
-def stream_roof(view, k, n_out, stream, launches=10):
+def stream_roof(view, k, n_out, stream, launches=8):
     """GB/s of the streaming probe over the workload's own blocks: k inputs
     read, n_out outputs written per stripe (outputs are the parity rows:
-    callers re-encode afterwards)."""
+    callers re-encode afterwards).  The best of its tile sizes and orders:
+    the rate this part reaches for that read:write mix."""
     import torch
 
     from paper_1312_5155_amd import binding as B
     S, n, nb = view.shape
-    args = (view.data_ptr(), n * nb, nb, S, k, n_out, nb)
-    for _ in range(3):
-        B.rs_poly_stream_probe(*args, stream=stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(launches):
-        B.rs_poly_stream_probe(*args, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / launches
-    return (k + n_out) * nb * S / (ms / 1e3) / 1e9
+    best = 0.0
+    for tile in (65536, 262144):
+        for order in (0, 1):
+            args = (view.data_ptr(), n * nb, nb, S, k, n_out, nb, tile, order)
+            for _ in range(2):
+                B.rs_poly_stream_probe(*args, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(launches):
+                B.rs_poly_stream_probe(*args, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / launches
+            best = max(best, (k + n_out) * nb * S / (ms / 1e3) / 1e9)
+    return best
 
 
 def plain_path(codes, stripes, erasures, stream, steps, user):

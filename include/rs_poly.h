@@ -202,8 +202,8 @@ int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures,
  * base + s * stripe_stride + b * block_stride (inputs b < n_in, outputs
  * n_in .. n_in + n_out - 1), reading every input byte once and writing
  * every output byte once (each output is the XOR of the inputs), with the
- * codec kernels' 16-byte non-temporal accesses and walk over column tiles
- * of tile_bytes, but no table lookups.  Its rate is the HBM bandwidth this
+ * codec kernels' 16-byte non-temporal accesses and walks over column tiles
+ * of tile_bytes (tile_order as in rs_poly_launch_t), but no table lookups.  Its rate is the HBM bandwidth this
  * part achieves for the read:write mix of an encode (n_in = k, n_out = m)
  * or a decode (k, t): the achievable roof beside the nominal peak.
  *   base        device pointer, 16-byte aligned; the caller owns the memory
@@ -214,10 +214,11 @@ int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures,
  *   n_in        1..RS_POLY_MAX_N;  n_out 1..RS_POLY_MAX_M
  *   block_bytes multiple of 16, at most 2^31
  *   tile_bytes  columns per tile: a multiple of 16, >= 4096
+ *   tile_order  0 or 1
  * Asynchronous on `stream`.  Errors: RS_ENULL, RS_EINVAL, RS_EDEVICE. */
 int rs_poly_stream_probe(uint8_t *base, size_t stripe_stride, size_t block_stride,
                          int stripes, int n_in, int n_out, size_t block_bytes,
-                         int tile_bytes, void *stream);
+                         int tile_bytes, int tile_order, void *stream);
 
 /* ------------------------------------------------------------ batches --
  *

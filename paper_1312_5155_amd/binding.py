@@ -66,7 +66,7 @@ def load():
     lib.rs_poly_bitmatrix_supported.argtypes = [i, i, i, u]
     lib.rs_poly_decode.argtypes = [vp, pp, sz, ip, i, u, vp]
     lib.rs_poly_decode_plan.argtypes = [vp, ip, i, u, ip, ip, u8p]
-    lib.rs_poly_stream_probe.argtypes = [vp, sz, sz, i, i, i, sz, i, vp]
+    lib.rs_poly_stream_probe.argtypes = [vp, sz, sz, i, i, i, sz, i, i, vp]
     sp = ctypes.POINTER(Stripe)
     lp = ctypes.POINTER(Launch)
     lib.rs_poly_batch_create.argtypes = [ctypes.POINTER(vp)]
@@ -330,9 +330,9 @@ def rs_poly_batch_noalloc(op, stripes, stream=None):
 
 
 def rs_poly_stream_probe(base, stripe_stride, block_stride, stripes, n_in, n_out, block_bytes,
-                         tile_bytes=65536, stream=None):
+                         tile_bytes=65536, tile_order=0, stream=None):
     return check(load().rs_poly_stream_probe(_ptr(base), stripe_stride, block_stride, stripes,
-                                             n_in, n_out, block_bytes, tile_bytes,
+                                             n_in, n_out, block_bytes, tile_bytes, tile_order,
                                              _stream(stream)), "rs_poly_stream_probe")
 
 

@@ -401,21 +401,23 @@ int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
 }
 
 int rs_poly_stream_probe(uint8_t *base, size_t stripe_stride, size_t block_stride, int stripes,
-                        int n_in, int n_out, size_t block_bytes, int tile_bytes, void *stream) {
+                        int n_in, int n_out, size_t block_bytes, int tile_bytes, int tile_order,
+                        void *stream) {
   if (!base) return RS_ENULL;
   if (stripes < 0 || n_in < 1 || n_in > RS_POLY_MAX_N || n_out < 1 || n_out > RS_POLY_MAX_M)
     return RS_EINVAL;
   if (pointer_alignment(base) < 16 || stripe_stride % 16 || block_stride % 16 ||
       block_bytes % 16 || block_bytes > kMaxPieceBytes || block_bytes > block_stride ||
       (uint64_t)(n_in + n_out) * block_stride > stripe_stride || tile_bytes < 4096 ||
-      tile_bytes % 16)
+      tile_bytes % 16 || (tile_order != 0 && tile_order != 1))
     return RS_EINVAL;
   if (stripes == 0 || block_bytes == 0) return RS_OK;
   const int ncu = device_cu_count();
   if (ncu <= 0) return RS_EDEVICE;
   return hip_status(launch_stream_probe(base, stripe_stride, block_stride, (uint32_t)stripes,
                                         (uint32_t)n_in, (uint32_t)n_out, (uint32_t)block_bytes,
-                                        (uint32_t)tile_bytes, 2 * ncu, stream));
+                                        (uint32_t)tile_bytes, (uint32_t)tile_order, 2 * ncu,
+                                        stream));
 }
 
 int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures, unsigned flags,

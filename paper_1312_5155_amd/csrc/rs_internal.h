@@ -145,10 +145,10 @@ constexpr uint32_t kBitmatrixTileCols = 2048;
 // output blocks of block_bytes (a multiple of 16) at base + s * stripe_stride
 // + b * block_stride; every input byte read once, every output byte written
 // once (the XOR of the inputs), tiles of tile_cols columns over `grid`
-// workgroups.  Returns a hipError_t as int.
+// workgroups in tile order 0 or 1.  Returns a hipError_t as int.
 int launch_stream_probe(uint8_t *base, uint64_t stripe_stride, uint64_t block_stride,
                         uint32_t stripes, uint32_t n_in, uint32_t n_out, uint32_t block_bytes,
-                        uint32_t tile_cols, int grid, void *stream);
+                        uint32_t tile_cols, uint32_t tile_order, int grid, void *stream);
 
 // Resident workgroups per CU the kernel is sized for (LDS bound).
 int codec_wgs_per_cu(Mode mode);

@@ -169,11 +169,12 @@ def test_stream_probe_validates_before_any_device_call():
     probe = lib.rs_poly_stream_probe
     base = ctypes.c_void_p(0x100000)
     MiB = 1 << 20
-    ok = dict(ss=14 * MiB, bs=MiB, st=4, ni=10, no=4, bb=MiB, tb=65536)
+    ok = dict(ss=14 * MiB, bs=MiB, st=4, ni=10, no=4, bb=MiB, tb=65536, to=0)
 
     def call(base=base, **kw):
         a = {**ok, **kw}
-        return probe(base, a["ss"], a["bs"], a["st"], a["ni"], a["no"], a["bb"], a["tb"], None)
+        return probe(base, a["ss"], a["bs"], a["st"], a["ni"], a["no"], a["bb"], a["tb"], a["to"],
+                     None)
 
     assert call(base=None) == B.RS_ENULL
     assert call(st=0) == B.RS_OK                             # nothing to stream
@@ -188,6 +189,7 @@ def test_stream_probe_validates_before_any_device_call():
     assert call(ss=13 * MiB) == B.RS_EINVAL                   # stripe holds 14 blocks
     assert call(tb=2048) == B.RS_EINVAL
     assert call(tb=65537) == B.RS_EINVAL
+    assert call(to=2) == B.RS_EINVAL
 
 
 def apply_plan_on_cpu(F, k, m, full, erasures, flags, code):

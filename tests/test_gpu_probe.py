@@ -22,14 +22,16 @@ def say(*a):
     (2, 32, 8, 65536, 8192),
     (1, 1, 1, 16, 4096),
     (4, 9, 2, 1 << 20, 65536),
+    (5, 3, 3, 1000 * 16, 4096),          # not a multiple of a wave's 2 KiB
 ])
-def test_stream_probe_writes_the_xor_of_its_inputs(S, n_in, n_out, nb, tile):
-    say(f"probe S={S} in={n_in} out={n_out} B={nb}")
+@pytest.mark.parametrize("order", [0, 1])
+def test_stream_probe_writes_the_xor_of_its_inputs(S, n_in, n_out, nb, tile, order):
+    say(f"probe S={S} in={n_in} out={n_out} B={nb} order={order}")
     bs = (nb + 255) // 256 * 256 + 256          # guard bytes after every block
     ss = (n_in + n_out) * bs + 256
     buf = workloads.device_random_blocks(torch, 91 + n_in, 1, S * ss)[0]
     ref = buf.clone()
-    B.rs_poly_stream_probe(buf.data_ptr(), ss, bs, S, n_in, n_out, nb, tile)
+    B.rs_poly_stream_probe(buf.data_ptr(), ss, bs, S, n_in, n_out, nb, tile, order)
     torch.cuda.synchronize()
     v, r = buf.view(S, ss), ref.view(S, ss)
     for s in range(S):
