@@ -531,6 +531,43 @@ def plain_encoders_leg(dev, stream, steps):
     return out
 
 
+def encoder_forms_leg(view, stripes, codes, stream, steps):
+    """The three encoders on the workload's own stripes, one launch per
+    stripe: the LFSR (rs_poly_encode), the bit-sliced XOR-only form
+    (rs_poly_encode_bitmatrix) and the generator-matrix form
+    (rs_poly_encode_matrix); each parity must equal the batched encode's
+    (already in the buffer)."""
+    import torch
+
+    from paper_1312_5155_amd import binding as B
+    S, n, nb = view.shape
+    k, m = stripes[0][0], stripes[0][1]
+    ref = view[:, k:].clone()
+    h = codes[(k, m)].handle
+    forms = {"lfsr": B.rs_poly_encode, "bitmatrix": B.rs_poly_encode_bitmatrix,
+             "matrix": B.rs_poly_encode_matrix}
+    out = {"workload": f"{S} stripes, one launch each", "alg_bytes": S * n * nb}
+    for label, fn in forms.items():
+        def step():
+            for (_, _, nbytes, p) in stripes:
+                fn(h, p[:k], p[k:], nbytes, stream)
+        view[:, k:] = 0
+        step()
+        torch.cuda.synchronize()
+        if not torch.equal(view[:, k:], ref):
+            raise SystemExit(f"{label} encode differs from the batched encode")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[label] = {"ms": round(ms, 3), "gbs": round(S * n * nb / (ms / 1e3) / 1e9, 1),
+                      "frac": round(S * n * nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def bitmatrix_batch_leg(batch, enc, view, stream, steps, warmup):
     """The batched encode again with the bit-sliced placement; the parity
     must equal the LFSR batch's."""
@@ -733,12 +770,14 @@ def main():
                                "sample": f"1 stripe window, {secs1:.1f} s"},
                "cpus_visible": avail, "cpu_model": cpu_model(),
                "gpu_parity_matches_oracle": True, "decode_restores_windows": True}
+    extras = {}
+    if args.extras and args.encoder_steps > 0 and view is not None:
+        extras["encoder_forms"] = encoder_forms_leg(view, stripes, codes, stream, 3)
     del buf, view, stripes, erasures, batch
     torch.cuda.empty_cache()
 
-    extras = {}
     if args.extras:
-        # serving first: in one full run, serving measured after all the
+        # serving next: in one full run, serving measured after all the
         # other legs reached about 40% of its capacity measured on its own,
         # or after any one of those legs (cause not isolated)
         if args.serving_requests > 0:

@@ -134,13 +134,14 @@ int rs_poly_bitmatrix_supported(int k, int m, int w, unsigned prim_poly);
 /* Encode in generator-matrix form (Sec. 6): the same parity bytes as
  * rs_poly_encode, computed as p = sum_j P[:, j] d_j with column P[:, j] the
  * remainder of x^(m+j) mod g(x), one packed table lookup per data block and
- * column and no serial LFSR chain.  The tables of all k blocks share one LDS
- * row, so the code must have k <= 8 (RS_POLY_MATRIX_MAX_K); it is the kernel
- * of rs_poly_update's matrix form, updating zero parity by the data.
+ * column and no serial LFSR chain.  Codes with k <= 8 run the kernel of
+ * rs_poly_update's matrix form (the k tables share one LDS row set),
+ * updating zero parity by the data; codes with 8 < k <= 32
+ * (RS_POLY_MATRIX_MAX_K) a wide form whose 32 tables fill two LDS regions.
  *   data, parity, block_bytes  as rs_poly_encode (any alignment)
- * Errors: RS_ENULL (h, data, parity, or an entry), RS_EINVAL (k > 8),
+ * Errors: RS_ENULL (h, data, parity, or an entry), RS_EINVAL (k > 32),
  * RS_EDEVICE. */
-#define RS_POLY_MATRIX_MAX_K 8
+#define RS_POLY_MATRIX_MAX_K 32
 int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data,
                           uint8_t *const *parity, size_t block_bytes, void *stream);
 

@@ -21,7 +21,7 @@ RS_ENOMEM = -6
 RS_EBUSY = -7
 RS_POLY_FLAG_ALL_SURVIVORS = 1
 RS_POLY_MAX_M = 8
-RS_POLY_MATRIX_MAX_K = 8
+RS_POLY_MATRIX_MAX_K = 32
 RS_POLY_MAX_N = 255
 
 _lib = None

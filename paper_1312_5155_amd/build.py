@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librs_poly.so")
 
 SOURCES = ["codec.hip", "bitmatrix.hip", "gf.cpp", "api.cpp", "batch.cpp", "serve.cpp",
-           "roof.hip", "noalloc.hip"]
+           "roof.hip", "noalloc.hip",
+           "nibble.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

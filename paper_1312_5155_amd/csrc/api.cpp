@@ -285,7 +285,7 @@ int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *con
                           size_t block_bytes, void *stream) {
   if (!h || !data || !parity) return RS_ENULL;
   const Code &c = h->code;
-  if (c.k() > kMatrixMaxBlocks) return RS_EINVAL;
+  if (c.k() > kMatrixWideMaxBlocks) return RS_EINVAL;
   int align = 16;
   for (int j = 0; j < c.k(); ++j) {
     if (!data[j]) return RS_ENULL;
@@ -297,9 +297,13 @@ int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *con
   }
   if (block_bytes == 0) return RS_OK;
   // The matrix-form update of every data block from zero parity: the same
-  // kernel, with the old-parity reads sent to the zero page.
+  // kernel, with the old-parity reads sent to the zero page.  Up to 8
+  // blocks the tables share one LDS row set (the kernel of rs_poly_update);
+  // more take the wide form, 32 tables in two LDS regions, built in the
+  // kernel from the column coefficients.
   int which[kMatrixMaxBlocks];
-  for (int j = 0; j < c.k(); ++j) which[j] = j;
+  for (int j = 0; j < c.k() && j < kMatrixMaxBlocks; ++j) which[j] = j;
+  const Mode mode = c.k() <= kMatrixMaxBlocks ? kUpdateMatrix : kUpdateMatrixWide;
 
   std::lock_guard<std::mutex> lock(h->mu);
   const int ncu = device_cu_count();
@@ -310,11 +314,26 @@ int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *con
     const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
     CodecParams p;
     memset(&p, 0, sizeof(p));
-    fill_matrix_update_params(c, data, parity, which, c.k(), off, piece, &p);
-    for (int i = 0; i < c.m(); ++i) p.par_in[i] = nullptr;
+    if (mode == kUpdateMatrix) {
+      fill_matrix_update_params(c, data, parity, which, c.k(), off, piece, &p);
+      for (int i = 0; i < c.m(); ++i) p.par_in[i] = nullptr;
+    } else {
+      for (int j = 0; j < c.k(); ++j) {
+        p.data[j] = data[j] + off;
+        memcpy(p.mat_coef[j], c.column(j), (size_t)c.m());
+      }
+      for (int i = 0; i < c.m(); ++i) p.out[i] = parity[i] + off;
+      p.block_bytes = piece;
+      p.k = c.k();
+      p.m = c.m();
+      p.k_pad = (c.k() + sb - 1) / sb * sb;
+      p.n_out = c.m();
+      p.field_poly = c.field().poly();
+      p.field_w = c.field().w();
+    }
     p.zero_page = zp;
-    const LaunchCfg cfg = default_cfg(kUpdateMatrix, sb, piece, align, ncu);
-    const int rc = hip_status(launch_codec(kUpdateMatrix, sb, p, cfg, stream));
+    const LaunchCfg cfg = default_cfg(mode, sb, piece, align, ncu);
+    const int rc = hip_status(launch_codec(mode, sb, p, cfg, stream));
     if (rc != RS_OK) return rc;
   }
   return RS_OK;

@@ -71,8 +71,11 @@ namespace {
 // A kernel variant (the MODE template argument below): the operation in the
 // low two bits, the LFSR table placement in the next one.
 constexpr int kNibbleBit = 4;
+constexpr int kWideMatrixBit = 8;   // kUpdateMatrixWide = kUpdateMatrix | this
 constexpr int op_of(int v) { return v & 3; }
 constexpr bool nibble_of(int v) { return (v & kNibbleBit) != 0; }
+constexpr bool wide_matrix_of(int v) { return (v & kWideMatrixBit) != 0; }
+static_assert(kUpdateMatrixWide == (kUpdateMatrix | kWideMatrixBit), "mode encoding");
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
   return __builtin_amdgcn_perm(hi, lo, sel);
@@ -177,12 +180,16 @@ struct Layout {
   static constexpr uint32_t kApplyReps = (kTwoRegions ? 256 : 128) / (M * kEntry);
   static constexpr uint32_t kTableBytes = kApplyReps * kEntry;    // one apply table
   static constexpr uint32_t kApplyBase = kTwoRegions ? 65536 : 128;
+  // Wide matrix form: 32 tables in two 64 KiB regions of 16 tables each.
+  static constexpr bool kWideMatrix = wide_matrix_of(MODE);
   static constexpr uint32_t kLdsBytes =
-      kTwoRegions ? 131072 : kNibble && op_of(MODE) != kDecode ? 32 * kRowBytes : 65536;
+      kTwoRegions || kWideMatrix ? 131072
+      : kNibble && op_of(MODE) != kDecode ? 32 * kRowBytes : 65536;
   // Matrix update: one table per changed block, a group of M tables per
   // item (the item's M blocks), kMatReps replicas; 2 groups per row for
-  // M = 4, 1 for M = 8 (8 tables at most).
-  static constexpr uint32_t kMatReps = M == 4 ? 8 : 4;
+  // M = 4, 1 for M = 8 (8 tables at most).  Wide form: 4 (M = 4) or 2
+  // (M = 8) groups per row, 16 tables per row and region.
+  static constexpr uint32_t kMatReps = kWideMatrix ? (M == 4 ? 4 : 2) : (M == 4 ? 8 : 4);
   static constexpr uint32_t kMatTableBytes = kMatReps * kEntry;
   static constexpr uint32_t kMatGroupBytes = M * kMatTableBytes;
   // Lane groups at different rotation phases: in one LDS read group g uses
@@ -343,6 +350,50 @@ __device__ void build_matrix_tables(uint8_t *lds, const uint32_t *basis /* [kMax
     const int tt = k_pad - 1 - (int)pos;
     return tt >= 0 && tt < c ? entry_of<M>(f, basis + 16 * tt, 0) : make_uint2(0u, 0u);
   });
+}
+
+// Product of a and b in GF(2^w) with field polynomial poly (shift and add).
+__device__ __forceinline__ uint32_t gf_mul(uint32_t a, uint32_t b, uint32_t poly, int w) {
+  uint32_t r = 0;
+  for (int i = 0; i < w; ++i) {
+    if ((b >> i) & 1u) r ^= a;
+    a <<= 1;
+    if (a >> w) a ^= poly;
+  }
+  return r;
+}
+
+// Expands the wide matrix-form tables (up to 32 blocks).  Window position
+// pos holds changed block t = k_pad - 1 - pos, its table in region pos / 16
+// at table index pos mod 16 of the row (group (pos mod 16) / M, slot pos
+// mod M).  The 8 basis values of each table (the products of its column
+// by the unit bytes) are computed here, from the column coefficients, into
+// `bases` first.
+template <int M>
+__device__ void build_wide_matrix_tables(uint8_t *lds, uint32_t (*bases)[16],
+                                         const CodecParams &p) {
+  using L = Layout<M, kUpdateMatrixWide>;
+  static_assert(16 * L::kMatTableBytes == kRowBytes, "16 tables per row and region");
+  const int m = p.m, c = p.k, k_pad = p.k_pad;
+  for (uint32_t idx = threadIdx.x; idx < kMatrixWideMaxBlocks * 8; idx += blockDim.x) {
+    const int pos = (int)idx / 8, b = (int)idx % 8;
+    const int t = k_pad - 1 - pos;
+    uint64_t v = 0;
+    if (t >= 0 && t < c && b < p.field_w)
+      for (int i = 0; i < m; ++i)   // byte i: coefficient m - 1 - i
+        v |= (uint64_t)gf_mul(p.mat_coef[t][m - 1 - i], 1u << b, p.field_poly, p.field_w)
+             << (8 * i);
+    if constexpr (M == 4) {
+      bases[pos][b] = (uint32_t)v;
+    } else {
+      bases[pos][2 * b] = (uint32_t)v;
+      bases[pos][2 * b + 1] = (uint32_t)(v >> 32);
+    }
+  }
+  __syncthreads();
+  for (int region = 0; region < 2; ++region)
+    fill_tables(lds + 65536 * region, 256, 0, 16, L::kMatTableBytes,
+                [&](uint32_t f, uint32_t tt) { return entry_of<M>(f, bases[16 * region + tt], 0); });
 }
 
 // Block pointers always address global memory; saying so keeps the
@@ -613,10 +664,23 @@ __device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const ui
 #pragma unroll
           for (int h = 0; h < NQ; ++h) acc[h] = 0;
           constexpr uint32_t kG = Layout<M, MODE>::kMatGroupBytes;
-          if (M == 8 || g == 0)
+          if constexpr (Layout<M, MODE>::kWideMatrix) {
+            // item g: region (g M) / 16, group ((g M) mod 16) / M of the row
+            const uint8_t *rl = lds + ((g * M) >> 4) * 65536;
+            const int gr = ((g * M) & 15) / M;
+            if (gr == 0)
+              matrix_lookups<M, MODE, 0>(d[0][x], d[NQ - 1][x], acc, rl, t);
+            else if (gr == 1)
+              matrix_lookups<M, MODE, kG>(d[0][x], d[NQ - 1][x], acc, rl, t);
+            else if (gr == 2)
+              matrix_lookups<M, MODE, 2 * kG>(d[0][x], d[NQ - 1][x], acc, rl, t);
+            else
+              matrix_lookups<M, MODE, 3 * kG>(d[0][x], d[NQ - 1][x], acc, rl, t);
+          } else if (M == 8 || g == 0) {
             matrix_lookups<M, MODE, 0>(d[0][x], d[NQ - 1][x], acc, lds, t);
-          else
+          } else {
             matrix_lookups<M, MODE, kG>(d[0][x], d[NQ - 1][x], acc, lds, t);
+          }
 #pragma unroll
           for (int h = 0; h < NQ; ++h) d[h][x] = acc[h];
         }
@@ -903,9 +967,13 @@ constexpr int max_threads() {
 // One stripe per launch: grid-stride loop over its column chunks.
 template <int M, int W, int MODE, bool BYTEWISE>
 __global__ void __launch_bounds__((max_threads<M, W, MODE>()))
-__attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) codec_kernel(CodecParams p) {
+__attribute__((amdgpu_waves_per_eu(M == 4 && !wide_matrix_of(MODE) ? 4 : 2)))
+codec_kernel(CodecParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[Layout<M, MODE>::kLdsBytes];
-  if constexpr (op_of(MODE) == kUpdateMatrix) {
+  if constexpr (Layout<M, MODE>::kWideMatrix) {
+    __shared__ uint32_t bases[kMatrixWideMaxBlocks][16];
+    build_wide_matrix_tables<M>(lds, bases, p);
+  } else if constexpr (op_of(MODE) == kUpdateMatrix) {
     build_matrix_tables<M>(lds, &p.apply_basis[0][0], p.k, p.k_pad);
   } else {
     build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
@@ -1089,6 +1157,7 @@ int launch_codec(Mode mode, int sb, const CodecParams &p, const LaunchCfg &cfg, 
     case kDecode: fn = pick<kDecode>(sb, w, cfg.bytewise); break;
     case kUpdate: fn = pick<kUpdate>(sb, w, cfg.bytewise); break;
     case kUpdateMatrix: fn = pick<kUpdateMatrix>(sb, w, cfg.bytewise); break;
+    case kUpdateMatrixWide: fn = pick<kUpdateMatrixWide>(sb, w, cfg.bytewise); break;
     default: return (int)hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.threads), 0,

@@ -72,6 +72,9 @@ class Code {
   // (Sec. 6): byte x maps to the remainder of x * x^(m+j) mod g(x), byte b
   // holding coefficient m-1-b.  16 dwords, as lfsr_basis().
   void column_basis(int j, uint32_t *basis) const;
+  // The m coefficients of x^(m+j) mod g(x), low degree first (column j of
+  // the generator matrix, Sec. 6).
+  const uint8_t *column(int j) const { return &pcol_[(size_t)j * m_]; }
   // Plan for the erasure list e[0..t), validated and sorted increasingly by
   // the caller; rebuilt symbol i is block e[i].  Cached (Opt3 of Sec. 4).
   std::shared_ptr<const DecodePlan> plan(const int *e, int t, unsigned flags);

@@ -9,6 +9,8 @@ namespace rsp {
 
 constexpr int kMaxN = 255;
 constexpr int kMaxM = 8;
+// Most blocks the wide generator-matrix form takes (see Mode).
+constexpr int kMatrixWideMaxBlocks = 32;
 
 // ---------------------------------------------------------------- tables --
 //
@@ -50,6 +52,13 @@ struct CodecParams {
   uint32_t lfsr_basis[16];        // 8 values of T'(2^b), 1 or 2 dwords each
   uint32_t apply_basis[kMaxM][16];// decode: per remainder byte, 8 values;
                                   // matrix update: per changed block
+  // Wide matrix form (up to kMatrixWideMaxBlocks blocks): the column of
+  // changed block t is mat_coef[t][0..m) (coefficients of x^(m+j) mod g,
+  // low degree first); the kernel builds its tables in GF(2^field_w) with
+  // the field polynomial field_poly.
+  uint8_t mat_coef[kMatrixWideMaxBlocks][kMaxM];
+  uint32_t field_poly;
+  int32_t field_w;
 };
 
 // kUpdate: parity ^= encode(delta) -- the encode LFSR over the changed data
@@ -57,7 +66,9 @@ struct CodecParams {
 // result from the generator-matrix columns of the (at most
 // kMatrixMaxBlocks) changed blocks, one packed lookup per changed block and
 // column; the apply bases then hold the columns' table bases.
-enum Mode : int { kEncode = 0, kDecode = 1, kUpdate = 2, kUpdateMatrix = 3 };
+// kUpdateMatrixWide: the matrix form for up to kMatrixWideMaxBlocks blocks,
+// its tables in two 64 KiB LDS regions (plain launches only).
+enum Mode : int { kEncode = 0, kDecode = 1, kUpdate = 2, kUpdateMatrix = 3, kUpdateMatrixWide = 11 };
 constexpr int kMatrixMaxBlocks = 8;
 
 // A launch configuration of the codec kernel.
@@ -149,6 +160,24 @@ constexpr uint32_t kBitmatrixTileCols = 2048;
 int launch_stream_probe(uint8_t *base, uint64_t stripe_stride, uint64_t block_stride,
                         uint32_t stripes, uint32_t n_in, uint32_t n_out, uint32_t block_bytes,
                         uint32_t tile_cols, uint32_t tile_order, int grid, void *stream);
+
+// Register-resident split-nibble update (nibble.hip): parity[i] ^= sum_t
+// P[i][j_t] * delta[t] for c changed blocks j_t, the product of each
+// (t, i) constant as two 16-entry nibble tables in registers; every pointer
+// 16-byte aligned, any block_bytes.
+constexpr int kNibbleMaxBlocks = 2;
+constexpr int kNibbleMaxProducts = 8;
+struct NibbleParams {
+  const uint8_t *delta[kNibbleMaxBlocks];
+  uint8_t *parity[kMaxM];
+  uint64_t block_bytes;
+  int32_t c, m;
+  // constant (t, i) at t * m + i: dwords 0-3 hold c * n for n < 16 (entry n
+  // at byte n), dwords 4-7 hold c * (n << 4)
+  uint32_t tab[kNibbleMaxProducts][8];
+};
+bool nibble_supported(int c, int m);
+int launch_nibble_update(const NibbleParams &p, int grid, void *stream);
 
 // Resident workgroups per CU the kernel is sized for (LDS bound).
 int codec_wgs_per_cu(Mode mode);

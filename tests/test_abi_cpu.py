@@ -130,7 +130,10 @@ def test_validation_happens_before_any_device_call():
     assert enc_mx(h6.handle, None, p6, 16, None) == B.RS_ENULL
     p6[1] = None
     assert enc_mx(h6.handle, d6, p6, 16, None) == B.RS_ENULL
-    assert enc_mx(h, d, p3, 16, None) == B.RS_EINVAL                 # k = 10 > 8
+    h33 = B.Code(33, 4)
+    d33 = (ctypes.c_void_p * 33)(*([0x1000] * 33))
+    assert enc_mx(h33.handle, d33, p3, 16, None) == B.RS_EINVAL      # k = 33 > 32
+    assert enc_mx(h, d, p3, 0, None) == B.RS_OK                      # k = 10: wide form
     # update: NULL delta entries are unchanged blocks; parity is required
     nod = (ctypes.c_void_p * 10)()
     p2 = (ctypes.c_void_p * 4)(*([0x2000] * 4))

@@ -244,6 +244,21 @@ def test_plain_update_both_forms_at_the_boundary():
             case.check()
 
 
+@pytest.mark.parametrize("k,m,changed", [(10, 4, [2, 7]), (32, 8, [0, 13, 31]),
+                                         (12, 4, list(range(12)))])
+def test_plain_update_large_aligned_blocks(k, m, changed):
+    # 4 MiB + 48-byte blocks on a 256-byte stride: 16-byte aligned, so the
+    # widest-load kernels run, with several rounds per lane (matrix form for
+    # up to 8 changed blocks, LFSR form for all 12)
+    nbytes = (4 << 20) + 48
+    say(f"plain update RS({k},{m}) B={nbytes} changed={len(changed)}")
+    case = UpdateCase(k, m, nbytes, changed, seed=900 + k, pad=256 - 48)
+    assert case.stride % 16 == 0 and case.dbuf.data_ptr() % 16 == 0
+    B.Code(k, m).update(case.delta_ptrs(), case.parity_ptrs(), nbytes)
+    torch.cuda.synchronize()
+    case.check()
+
+
 def test_batch_update_equals_plain_update():
     say("batch update vs plain")
     cases = batch_cases(62, 12, ((10, 4), (32, 8)), 4096, 1 << 20)
