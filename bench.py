@@ -16,8 +16,10 @@ launch / launch time from HIP events on the launch stream) and against the
 achievable rate of a streaming probe with the same read:write mix; the CPU
 oracle timed on a bounded sample of the same stripes on this host; and, as
 extra keys, the RS(10,4) 256 x 1 MiB batch (with the delta-parity update and
-the bit-sliced encode), the 4096 mixed uneven stripes, and the serving
-workload swept over offered load.
+the bit-sliced encode), the 4096 mixed uneven stripes, the serving
+workload swept over offered load, the encoder forms on the headline stripes,
+and one-stripe encoders and update forms (LDS tables vs register-held
+split-nibble products) on large blocks.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5]
 """
@@ -531,6 +533,58 @@ def plain_encoders_leg(dev, stream, steps):
     return out
 
 
+def nibble_update_leg(dev, stream, steps):
+    """One-stripe delta-parity updates on large blocks, 1 or 2 changed
+    blocks: the register-held split-nibble kernel (rs_poly_update_nibble)
+    against the LDS-table matrix form (rs_poly_update).  Both start from
+    the same parity and must end with identical bytes."""
+    import torch
+
+    from paper_1312_5155_amd import binding as B
+    import workloads
+    out = {}
+    for (k, m, nb, changed) in ((10, 4, 64 << 20, [3]), (10, 4, 64 << 20, [2, 7]),
+                                (32, 8, 16 << 20, [5]), (6, 3, 64 << 20, [0, 4])):
+        code = B.Code(k, m)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(workloads.data_seed(3) + 100 + k + len(changed))
+        delta = torch.randint(0, 256, (len(changed), nb), dtype=torch.uint8, device=dev,
+                              generator=gen)
+        par = torch.randint(0, 256, (2, m, nb), dtype=torch.uint8, device=dev, generator=gen)
+        par[1] = par[0]
+        dp = [None] * k
+        for t, j in enumerate(changed):
+            dp[j] = delta[t].data_ptr()
+        runs = {"nibble": (B.rs_poly_update_nibble, 0), "lds_matrix": (B.rs_poly_update, 1)}
+        for label, (fn, row) in runs.items():
+            fn(code.handle, dp, [par[row, i].data_ptr() for i in range(m)], nb, stream)
+        torch.cuda.synchronize()
+        if not torch.equal(par[0], par[1]):
+            raise SystemExit(f"RS({k},{m}) nibble update differs from the LDS update")
+        alg = (len(changed) + 2 * m) * nb
+        rec = {"changed_blocks": len(changed), "products": len(changed) * m, "alg_bytes": alg}
+        for label, (fn, row) in runs.items():
+            pp = [par[row, i].data_ptr() for i in range(m)]
+            for _ in range(4):
+                fn(code.handle, dp, pp, nb, stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+            for a, b in ev:
+                a.record(stream)
+                fn(code.handle, dp, pp, nb, stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+            ms = median([a.elapsed_time(b) for a, b in ev])
+            rec[label] = {"median_ms": round(ms, 4),
+                          "gbs": round(alg / (ms / 1e3) / 1e9, 1),
+                          "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rec["identical"] = True
+        out[f"RS({k},{m}) {nb >> 20} MiB blocks, changed {changed}"] = rec
+        del delta, par
+        torch.cuda.empty_cache()
+    return out
+
+
 def encoder_forms_leg(view, stripes, codes, stream, steps):
     """The three encoders on the workload's own stripes, one launch per
     stripe: the LFSR (rs_poly_encode), the bit-sliced XOR-only form
@@ -800,6 +854,7 @@ def main():
             torch.cuda.empty_cache()
         if args.encoder_steps > 0:
             extras["plain_encoders"] = plain_encoders_leg(dev, stream, args.encoder_steps)
+            extras["plain_update_forms"] = nibble_update_leg(dev, stream, args.encoder_steps)
 
     out = {
         "metric": METRIC, "value": head["value"], "unit": "GB/s", "n_gpus": 1,

@@ -165,6 +165,23 @@ int rs_poly_encode_matrix(rs_poly_t *h, const uint8_t *const *data,
 int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta,
                    uint8_t *const *parity, size_t block_bytes, void *stream);
 
+/* The same delta-parity update as rs_poly_update (Sec. 3.2 update property,
+ * generator-matrix columns of Sec. 6), computed with the split-nibble
+ * multiply held in registers instead of LDS tables: per changed block j and
+ * parity i, P[i][j] * x = P[i][j] * (x & 15) ^ P[i][j] * (x & 0xF0), each a
+ * 16-entry table looked up 4 bytes at a time.  No LDS, no transposes; one
+ * pass reading the changed blocks and the parity, writing the parity.
+ *   delta, parity, block_bytes, stream  as for rs_poly_update
+ * Limits: 1 or 2 changed (non-NULL) delta blocks with (changed * m) <= 8;
+ * every changed delta block and every parity block 16-byte aligned (any
+ * block_bytes: the last block_bytes mod 16 bytes are done byte by byte).
+ * No changed block, or block_bytes = 0, is a successful no-op.
+ * Errors: RS_ENULL (h, delta, parity, or a parity entry), RS_EINVAL (more
+ * changed blocks or products than the limits, or an unaligned pointer),
+ * RS_EDEVICE. */
+int rs_poly_update_nibble(rs_poly_t *h, const uint8_t *const *delta,
+                          uint8_t *const *parity, size_t block_bytes, void *stream);
+
 /* Erasure decode (Sec. 3.3): rebuilds, in place, exactly the blocks named in
  * erasures[0..n_erasures), data or parity, from the surviving blocks.
  *   blocks      host array of n = k+m device pointers, API block order

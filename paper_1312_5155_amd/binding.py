@@ -61,6 +61,7 @@ def load():
     lib.rs_poly_generator.argtypes = [vp, u8p]
     lib.rs_poly_encode.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_update.argtypes = [vp, pp, pp, sz, vp]
+    lib.rs_poly_update_nibble.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_encode_bitmatrix.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_encode_matrix.argtypes = [vp, pp, pp, sz, vp]
     lib.rs_poly_bitmatrix_supported.argtypes = [i, i, i, u]
@@ -243,6 +244,12 @@ def rs_poly_update(h, delta, parity, block_bytes, stream=None):
                  "rs_poly_update")
 
 
+def rs_poly_update_nibble(h, delta, parity, block_bytes, stream=None):
+    d, p = _ptr_array(delta), _ptr_array(parity)
+    return check(load().rs_poly_update_nibble(h, d, p, block_bytes, _stream(stream)),
+                 "rs_poly_update_nibble")
+
+
 def rs_poly_decode(h, blocks, block_bytes, erasures, flags=0, stream=None):
     b = _ptr_array(blocks)
     er = (ctypes.c_int * max(1, len(erasures)))(*erasures)
@@ -406,7 +413,7 @@ class Code:
 
     def encode_matrix(self, data, parity, block_bytes=None, stream=None):
         """The same parity as encode, from the generator-matrix kernel
-        (codes with k <= 8)."""
+        (codes with k <= 32)."""
         if block_bytes is None:
             block_bytes = data[0].numel()
         return rs_poly_encode_matrix(self._h, list(data), list(parity), block_bytes, stream)
@@ -417,6 +424,13 @@ class Code:
         if block_bytes is None:
             block_bytes = parity[0].numel()
         return rs_poly_update(self._h, list(delta), list(parity), block_bytes, stream)
+
+    def update_nibble(self, delta, parity, block_bytes=None, stream=None):
+        """The same update with register-held split-nibble products (1 or 2
+        changed blocks, changed * m <= 8, 16-byte-aligned blocks)."""
+        if block_bytes is None:
+            block_bytes = parity[0].numel()
+        return rs_poly_update_nibble(self._h, list(delta), list(parity), block_bytes, stream)
 
     def decode(self, blocks, erasures, block_bytes=None, flags=0, stream=None):
         if block_bytes is None:

@@ -381,6 +381,52 @@ int rs_poly_update(rs_poly_t *h, const uint8_t *const *delta, uint8_t *const *pa
   return RS_OK;
 }
 
+int rs_poly_update_nibble(rs_poly_t *h, const uint8_t *const *delta, uint8_t *const *parity,
+                          size_t block_bytes, void *stream) {
+  if (!h || !delta || !parity) return RS_ENULL;
+  const Code &c = h->code;
+  int which[kMatrixMaxBlocks];
+  const int changed = update_changed(c, delta, which);
+  for (int i = 0; i < c.m(); ++i)
+    if (!parity[i]) return RS_ENULL;
+  if (changed == 0) return RS_OK;
+  if (!nibble_supported(changed, c.m())) return RS_EINVAL;
+  for (int t = 0; t < changed; ++t)
+    if (pointer_alignment(delta[which[t]]) < 16) return RS_EINVAL;
+  for (int i = 0; i < c.m(); ++i)
+    if (pointer_alignment(parity[i]) < 16) return RS_EINVAL;
+  if (block_bytes == 0) return RS_OK;
+  // Per (changed block t, parity i) the two 16-entry tables of the constant
+  // P[i][j], the column j of the generator matrix (Sec. 6): the products by
+  // the low nibbles n and by the high nibbles n << 4, entry n in byte n.
+  NibbleParams p;
+  memset(&p, 0, sizeof(p));
+  const Field &f = c.field();
+  for (int t = 0; t < changed; ++t) {
+    p.delta[t] = delta[which[t]];
+    const uint8_t *col = c.column(which[t]);
+    for (int i = 0; i < c.m(); ++i) {
+      uint8_t lo[16], hi[16];
+      for (int n = 0; n < 16; ++n) {
+        lo[n] = f.mul(col[i], (uint8_t)n);
+        hi[n] = f.w() == 8 ? f.mul(col[i], (uint8_t)(n << 4)) : 0;
+      }
+      memcpy(&p.tab[t * c.m() + i][0], lo, 16);
+      memcpy(&p.tab[t * c.m() + i][4], hi, 16);
+    }
+  }
+  for (int i = 0; i < c.m(); ++i) p.parity[i] = parity[i];
+  p.block_bytes = block_bytes;
+  p.c = changed;
+  p.m = c.m();
+  std::lock_guard<std::mutex> lock(h->mu);
+  const int ncu = device_cu_count();
+  if (ncu <= 0) return RS_EDEVICE;
+  const uint64_t chunks = std::max<uint64_t>(1, block_bytes / 16);
+  const int grid = (int)std::min<uint64_t>((chunks + 511) / 512, (uint64_t)ncu * 8);
+  return hip_status(launch_nibble_update(p, grid, stream));
+}
+
 int rs_poly_decode(rs_poly_t *h, uint8_t *const *blocks, size_t block_bytes,
                    const int *erasures, int n_erasures, unsigned flags, void *stream) {
   if (!h) return RS_ENULL;

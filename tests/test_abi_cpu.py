@@ -121,7 +121,7 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_bitmatrix_supported(32, 8, 8, 0x11D) == 1
     assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x12B) == 0
     assert lib.rs_poly_bitmatrix_supported(4, 3, 4, 0x13) == 0
-    # generator-matrix encode: k <= 8 only
+    # generator-matrix encode: k <= 32
     enc_mx = lib.rs_poly_encode_matrix
     h6 = B.Code(6, 3)
     d6 = (ctypes.c_void_p * 6)(*([0x1000] * 6))
@@ -143,6 +143,41 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_update(h, d, None, 16, None) == B.RS_ENULL
     assert lib.rs_poly_update(None, d, p2, 16, None) == B.RS_ENULL
     assert lib.rs_poly_update(h, nod, p, 16, None) == B.RS_ENULL   # p[2] is NULL
+
+
+def test_nibble_update_validates_before_any_device_call():
+    # No GPU here: every case below must return before a HIP call.
+    lib = B.load()
+    upd = lib.rs_poly_update_nibble
+    code = B.Code(10, 4)          # kept alive: the handle is freed with it
+    h = code.handle
+    p4 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
+    one = (ctypes.c_void_p * 10)(*([None] * 9 + [0x1000]))
+    two = (ctypes.c_void_p * 10)(*([0x1000, None, None, 0x3000] + [None] * 6))
+    three = (ctypes.c_void_p * 10)(*([0x1000, 0x1010, 0x1020] + [None] * 7))
+    nod = (ctypes.c_void_p * 10)()
+    assert upd(h, nod, p4, 4096, None) == B.RS_OK        # nothing changed
+    assert upd(h, one, p4, 0, None) == B.RS_OK           # empty
+    assert upd(h, two, p4, 0, None) == B.RS_OK           # 2 x 4 = 8 products
+    assert upd(h, three, p4, 16, None) == B.RS_EINVAL    # 3 changed blocks
+    assert upd(None, one, p4, 16, None) == B.RS_ENULL
+    assert upd(h, None, p4, 16, None) == B.RS_ENULL
+    assert upd(h, one, None, 16, None) == B.RS_ENULL
+    p4[1] = None
+    assert upd(h, one, p4, 16, None) == B.RS_ENULL
+    p4[1] = 0x2008                                        # 8-byte aligned parity
+    assert upd(h, one, p4, 16, None) == B.RS_EINVAL
+    p4[1] = 0x2000
+    one[9] = 0x1004                                       # 4-byte aligned delta
+    assert upd(h, one, p4, 16, None) == B.RS_EINVAL
+    # RS(6,6): one changed block gives 6 products, two give 12 > 8
+    code6 = B.Code(6, 6)
+    h6 = code6.handle
+    p6 = (ctypes.c_void_p * 6)(*([0x2000] * 6))
+    d1 = (ctypes.c_void_p * 6)(*([0x1000] + [None] * 5))
+    d2 = (ctypes.c_void_p * 6)(*([0x1000, 0x1000] + [None] * 4))
+    assert upd(h6, d1, p6, 0, None) == B.RS_OK
+    assert upd(h6, d2, p6, 16, None) == B.RS_EINVAL
 
 
 def test_boundary_names_of_the_batch_calls():

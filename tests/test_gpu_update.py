@@ -335,3 +335,77 @@ def test_full_size_rs104_256x1MiB_batch_update():
         d = old[s, :, lo:hi].cpu().numpy().copy()
         d[int(changed[s])] ^= delta[s, lo:hi].cpu().numpy()
         assert np.array_equal(par[s, :, lo:hi].cpu().numpy(), oracle.encode(F, k, m, d)), s
+
+
+# Register-held split-nibble update (rs_poly_update_nibble): the same parity
+# as the LDS-table kernels, for 1 or 2 changed blocks with changed * m <= 8.
+# Block strides are multiples of 16 so every block is 16-byte aligned; the
+# sizes cover a tail-only block (B < 16), one chunk plus a tail, several
+# grid strides with a ragged tail, and m above 4.
+NIBBLE = [(10, 4, 100003, [3]), (10, 4, 100003, [0, 9]), (10, 4, 15, [5]), (10, 4, 17, [1, 2]),
+          (10, 4, 16, [7]), (6, 6, 65551, [2]), (32, 8, 70001, [31]), (3, 7, 333, [1]),
+          (6, 3, 8191, [1, 4]), (12, 2, 4097, [0, 11]), (8, 1, 1000, [3, 5]), (1, 1, 1, [0]),
+          (13, 1, 999, [12]), (247, 8, 4112, [100])]
+
+
+def _aligned_pad(nbytes, extra=16):
+    return (-nbytes) % 16 + extra
+
+
+@pytest.mark.parametrize("k,m,nbytes,changed", NIBBLE)
+def test_nibble_update_matches_oracle(k, m, nbytes, changed):
+    say(f"nibble update k={k} m={m} B={nbytes} changed={changed}")
+    case = UpdateCase(k, m, nbytes, changed, seed=k * 37 + m * 5 + nbytes,
+                      pad=_aligned_pad(nbytes))
+    assert case.stride % 16 == 0
+    B.Code(k, m).update_nibble(case.delta_ptrs(), case.parity_ptrs(), nbytes)
+    torch.cuda.synchronize()
+    case.check()
+
+
+def test_nibble_update_gf16():
+    say("nibble update GF(2^4)")
+    for (k, m, changed) in ((4, 3, [0]), (9, 5, [3]), (12, 3, [0, 11]), (7, 4, [2, 6])):
+        case = UpdateCase(k, m, 777, changed, seed=k * 11 + m, w=4, poly=0x13,
+                          pad=_aligned_pad(777))
+        B.Code(k, m, 4, 0x13).update_nibble(case.delta_ptrs(), case.parity_ptrs(), 777)
+        torch.cuda.synchronize()
+        case.check()
+
+
+def test_nibble_update_twice_restores_parity():
+    say("nibble update twice")
+    case = UpdateCase(10, 4, 1 << 16, [1, 8], seed=43)
+    code = B.Code(10, 4)
+    for _ in range(2):
+        code.update_nibble(case.delta_ptrs(), case.parity_ptrs(), 1 << 16)
+    torch.cuda.synchronize()
+    case.check(want=case.parity0)
+
+
+@pytest.mark.parametrize("k,m,changed", [(10, 4, [2, 7]), (10, 4, [9]), (32, 8, [0])])
+def test_nibble_update_large_blocks_equal_the_lds_update(k, m, changed):
+    # 4 MiB + 48-byte blocks: many grid-stride rounds; the result equals the
+    # oracle's encoding of the new data and, byte for byte, what the
+    # LDS-table update makes of the same delta from the same parity
+    nbytes = (4 << 20) + 48
+    say(f"nibble update large RS({k},{m}) changed={changed}")
+    case = UpdateCase(k, m, nbytes, changed, seed=700 + k + len(changed), pad=256 - 48)
+    ref = case.pbuf.clone()
+    code = B.Code(k, m)
+    code.update_nibble(case.delta_ptrs(), case.parity_ptrs(), nbytes)
+    base = ref.data_ptr() + case.offset
+    code.update(case.delta_ptrs(), [base + i * case.stride for i in range(m)], nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(case.pbuf, ref)
+    case.check()
+
+
+def test_nibble_update_rejects_beyond_its_limits():
+    case = UpdateCase(10, 4, 4096, [0, 1, 2], seed=44)
+    code = B.Code(10, 4)
+    with pytest.raises(B.RsPolyError) as ei:
+        code.update_nibble(case.delta_ptrs(), case.parity_ptrs(), 4096)
+    assert ei.value.code == B.RS_EINVAL
+    torch.cuda.synchronize()
+    case.check(want=case.parity0)     # nothing was touched
