@@ -490,15 +490,17 @@ def update_leg(view, stripes, codes, batch, stream, steps, dev):
 
 def plain_encoders_leg(dev, stream, steps):
     """One-stripe launches of the three encoders on large blocks: the LFSR
-    (rs_poly_encode), the generator-matrix form (rs_poly_encode_matrix, for
-    RS(6,3): k <= 8) and the bit-sliced XOR-only form
-    (rs_poly_encode_bitmatrix); every parity must be identical."""
+    (rs_poly_encode), the generator-matrix form (rs_poly_encode_matrix) and
+    the bit-sliced XOR-only form (rs_poly_encode_bitmatrix: compiled-in XOR
+    networks for the workload codes, matrices taken at run time for
+    RS(16,4)); every parity must be identical."""
     import torch
 
     from paper_1312_5155_amd import binding as B
     import workloads
     out = {}
-    for (k, m, nb) in ((10, 4, 64 << 20), (6, 3, 64 << 20), (32, 8, 16 << 20)):
+    for (k, m, nb) in ((10, 4, 64 << 20), (6, 3, 64 << 20), (32, 8, 16 << 20),
+                       (16, 4, 32 << 20)):
         code = B.Code(k, m)
         gen = torch.Generator(device=dev)
         gen.manual_seed(workloads.data_seed(3) + k)

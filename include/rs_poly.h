@@ -117,18 +117,20 @@ int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data,
  * parity p_i = sum_j c_ij d_j with c_ij the coefficient of x^i in
  * x^(m+j) mod g(x) (the generator-matrix columns of Sec. 6), where each
  * product by c_ij is an 8 x 8 matrix over GF(2) applied to the bit planes
- * of the data bytes.  The XOR networks are fixed when the library is
- * built, so only the codes that rs_poly_bitmatrix_supported accepts run.
+ * of the data bytes.  Codes with k <= 32 run, over either field: for
+ * RS(6,3), RS(10,4), RS(12,4) and RS(32,8) over GF(2^8) with polynomial
+ * 0x11D the XOR networks are compiled into straight-line code; every other
+ * code takes its matrices at run time (8 masked XORs per matrix row).
  *   data, parity, block_bytes  as rs_poly_encode; every pointer must be
  *            16-byte aligned (any block_bytes)
- * Errors: RS_ENULL (h, data, parity, or an entry), RS_EINVAL (code not
- * built in, or a pointer not 16-byte aligned), RS_EDEVICE. */
+ * Errors: RS_ENULL (h, data, parity, or an entry), RS_EINVAL (k > 32, or a
+ * pointer not 16-byte aligned), RS_EDEVICE. */
 int rs_poly_encode_bitmatrix(rs_poly_t *h, const uint8_t *const *data,
                              uint8_t *const *parity, size_t block_bytes, void *stream);
 
 /* 1 if rs_poly_encode_bitmatrix runs the code (k, m) over GF(2^w) with
- * polynomial prim_poly, else 0: built in are RS(6,3), RS(10,4), RS(12,4)
- * and RS(32,8) over GF(2^8) with polynomial 0x11D.  Host only. */
+ * polynomial prim_poly (a code rs_poly_init accepts, with k <= 32), else 0.
+ * Host only. */
 int rs_poly_bitmatrix_supported(int k, int m, int w, unsigned prim_poly);
 
 /* Encode in generator-matrix form (Sec. 6): the same parity bytes as
@@ -288,7 +290,7 @@ typedef struct rs_poly_launch {
 #define RS_POLY_TABLES_NIBBLE 1
 /* Encode only: no tables -- the bit-sliced XOR-only kernel of
  * rs_poly_encode_bitmatrix, for a state width whose stripes in the call all
- * use one code that rs_poly_bitmatrix_supported accepts (any other call runs
+ * use one code with k <= 32 (any other call runs
  * the PACKED tables with the same launch shape).  Tiles are rounded down to
  * a multiple of 2048 columns; bytes_per_lane does not apply. */
 #define RS_POLY_TABLES_BITMATRIX 2

@@ -254,14 +254,16 @@ int rs_poly_encode(rs_poly_t *h, const uint8_t *const *data, uint8_t *const *par
 }
 
 int rs_poly_bitmatrix_supported(int k, int m, int w, unsigned poly) {
-  return bitmatrix_supported(k, m, w, poly) ? 1 : 0;
+  Code c;
+  return k <= kBitmatrixMaxK && c.init(k, m, w, poly) == RS_OK && c.bitmatrix() ? 1 : 0;
 }
 
 int rs_poly_encode_bitmatrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *const *parity,
                              size_t block_bytes, void *stream) {
   if (!h || !data || !parity) return RS_ENULL;
   const Code &c = h->code;
-  if (!bitmatrix_supported(c.k(), c.m(), c.field().w(), c.field().poly())) return RS_EINVAL;
+  const BitmatrixCode *bc = c.bitmatrix();
+  if (!bc) return RS_EINVAL;   // k above kBitmatrixMaxK
   for (int j = 0; j < c.k(); ++j) {
     if (!data[j]) return RS_ENULL;
     if (pointer_alignment(data[j]) < 16) return RS_EINVAL;
@@ -275,7 +277,7 @@ int rs_poly_encode_bitmatrix(rs_poly_t *h, const uint8_t *const *data, uint8_t *
   std::lock_guard<std::mutex> lock(h->mu);
   for (uint64_t off = 0; off < block_bytes; off += kMaxPieceBytes) {
     const uint64_t piece = std::min<uint64_t>(kMaxPieceBytes, block_bytes - off);
-    const int rc = hip_status(launch_bitmatrix(c.k(), c.m(), data, parity, off, piece, stream));
+    const int rc = hip_status(launch_bitmatrix(*bc, data, parity, off, piece, stream));
     if (rc != RS_OK) return rc;
   }
   return RS_OK;

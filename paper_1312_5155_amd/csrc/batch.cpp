@@ -143,7 +143,7 @@ struct rs_poly_batch {
   void drop_graphs_of(int wide);
   int ensure_staging(int i, const size_t *bytes);
   int ensure_group(int wide, size_t arena_bytes, uint64_t tiles, uint32_t stripes);
-  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, int bm_k, int bm_m,
+  int graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, const BitmatrixCode *bm,
                 hipGraphExec_t *out);
   int run(int op, const rs_poly_stripe_t *stripes, int count, void *stream);
 };
@@ -246,11 +246,12 @@ int rs_poly_batch::ensure_group(int wide, size_t arena_bytes, uint64_t tiles,
   return RS_OK;
 }
 
-int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si, int bm_k,
-                             int bm_m, hipGraphExec_t *out) {
+int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int si,
+                             const BitmatrixCode *bm, hipGraphExec_t *out) {
   GroupBuf &gb = groups[wide];
+  // (the bit-sliced kernels take the code's rows by value: one graph per code)
   const GraphKey key{op,          wide, cfg.bytes_per_lane, cfg.threads, cfg.wgs_per_cu,
-                     cfg.table_placement, si, gb.version, bm_k * 256 + bm_m};
+                     cfg.table_placement, si, gb.version, bm ? bm->key : 0};
   auto it = graphs.find(key);
   if (it != graphs.end()) {
     *out = it->second.exec;
@@ -265,8 +266,7 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int 
   lc.grid = num_cu * cfg.wgs_per_cu;
   lc.bytewise = false;
   lc.nibble = cfg.table_placement == RS_POLY_TABLES_NIBBLE;
-  lc.bm_k = bm_k;
-  lc.bm_m = bm_m;
+  lc.bm = bm;
   GraphEntry e;
   const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
                     : op == RS_POLY_OP_UPDATE ? kUpdate
@@ -372,11 +372,7 @@ int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
                      c.field().w() == first->field().w() &&
                      c.field().poly() == first->field().poly();
       }
-      if (one_code && first &&
-          bitmatrix_supported(first->k(), first->m(), first->field().w(), first->field().poly())) {
-        plan[w].bm_k = first->k();
-        plan[w].bm_m = first->m();
-      }
+      if (one_code && first) plan[w].bm = first->bitmatrix();   // nullptr for k > 32
     }
   }
 
@@ -488,7 +484,7 @@ int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
     uint64_t tc = std::min<uint64_t>((uint64_t)lc.tile_bytes, std::max<uint64_t>(4096, want));
     tc = tc / 16 * 16;
     // the bit-sliced kernel's waves take whole 2048-column chunks
-    if (gp.bm_k) tc = std::max<uint64_t>(kBitmatrixTileCols, tc / kBitmatrixTileCols * kBitmatrixTileCols);
+    if (gp.bm) tc = std::max<uint64_t>(kBitmatrixTileCols, tc / kBitmatrixTileCols * kBitmatrixTileCols);
     gp.tile_cols = (uint32_t)tc;
     uint64_t t = 0;
     for (auto &d : gp.descs) {
@@ -559,8 +555,8 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   for (int w = 0; w < kWidths; ++w) {
     if (plan[w].descs.empty()) continue;
     hipGraphExec_t exec;
-    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], si, plan[w].bm_k,
-                   plan[w].bm_m, &exec);
+    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], si, plan[w].bm,
+                   &exec);
     if (rc != RS_OK) return rc;
     if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
   }

@@ -43,7 +43,7 @@ struct GroupPlan {
   };
   std::map<MatrixKey, uint32_t> matrix_index;
   bool matrix = false;   // update group in the generator-matrix form
-  int bm_k = 0, bm_m = 0;  // encode group of one RS(bm_k, bm_m) code, bit-sliced
+  const BitmatrixCode *bm = nullptr;  // encode group of one code, bit-sliced
   std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
   uint64_t tiles = 0;
   uint32_t tile_cols = 0;

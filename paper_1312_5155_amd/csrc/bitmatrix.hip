@@ -296,16 +296,13 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-// Persistent batch kernel: the tile loop of the table-driven batch kernel
-// (same arena, tile map and claim counter; tile_cols a multiple of 2048),
-// with the bit-sliced encode in place of the LFSR: the waves of a
-// workgroup take neighbouring 2048-column chunks of the tile.  Every
-// stripe of the group is an RS(K, M) stripe.
-// (at most 2 workgroups of at most 1024 threads per CU: 4 waves per SIMD at
-// 512 threads, so the kernel may use 128 VGPRs and spill nothing)
-template <int K, int M>
-__global__ void __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(4))) bitmatrix_batch_kernel(BatchGroup g) {
+// The tile loop of the persistent batch kernels (same arena, tile map and
+// claim counter as the table-driven batch kernel; tile_cols a multiple of
+// 2048): the waves of a workgroup take neighbouring 2048-column chunks of
+// each tile they claim, chunk(stripe pointer table, first column, end
+// column, lane) encoding one.
+template <class Chunk>
+__device__ __forceinline__ void batch_tiles(const BatchGroup &g, Chunk &&chunk) {
   __shared__ uint64_t next_claim;
   BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
   const const_as<BatchHeader> chdr = (const_as<BatchHeader>)(uintptr_t)hdr;
@@ -339,12 +336,135 @@ __attribute__((amdgpu_waves_per_eu(4))) bitmatrix_batch_kernel(BatchGroup g) {
       const uint64_t bytes = descs[s].block_bytes;
       const uint64_t c0 = (tile - descs[s].tile_begin) * tile_cols;
       const uint64_t c1 = bytes - c0 > tile_cols ? c0 + tile_cols : bytes;
-      const TableBlocks<K, M> src{ptr_table + descs[s].ptr_off};
+      const const_as<uint64_t> ptrs = ptr_table + descs[s].ptr_off;
       for (uint64_t cc = c0 + (uint64_t)wave * kWaveCols; cc < c1; cc += (uint64_t)waves * kWaveCols)
-        encode_chunk<K, M>(src, cc, c1, lane);
+        chunk(ptrs, cc, c1, lane);
     }
     __syncthreads();   // next_claim is about to change
   }
+}
+
+// Persistent batch kernel of a compiled-in code: every stripe of the group
+// is an RS(K, M) stripe.
+// (at most 2 workgroups of at most 1024 threads per CU: 4 waves per SIMD at
+// 512 threads, so the kernel may use 128 VGPRs and spill nothing)
+template <int K, int M>
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(4))) bitmatrix_batch_kernel(BatchGroup g) {
+  batch_tiles(g, [](const_as<uint64_t> ptrs, uint64_t cc, uint64_t c1, uint32_t lane) {
+    encode_chunk<K, M>(TableBlocks<K, M>{ptrs}, cc, c1, lane);
+  });
+}
+
+// ---------------------------------------------------- runtime coefficients --
+//
+// Any code with k <= kBitmatrixMaxK over any field: the GF(2) rows of the
+// products come with the launch (rows.r[j][i][b]: bit b' set when bit b of
+// c_ij * 2^b' is), and each output plane is the XOR of the data planes its
+// row selects, as AND with an all-ones or all-zero mask made from the row
+// on the scalar unit: 8 vector operations per row whatever its bits, where
+// the compiled-in networks skip the zero bits.
+
+struct BitmatrixRtParams {
+  BitmatrixParams io;
+  int32_t k;
+  BitRows rows;
+};
+
+struct BitmatrixRtBatch {
+  BatchGroup g;
+  int32_t k;
+  BitRows rows;
+};
+
+// Pointer-table blocks with the code's k known at run time.
+struct TableBlocksRt {
+  const_as<uint64_t> ptrs;
+  int k, m;
+  __device__ const uint8_t *data(int j) const {
+    return reinterpret_cast<const uint8_t *>(ptrs[j]);
+  }
+  __device__ uint8_t *parity(int i) const { return reinterpret_cast<uint8_t *>(ptrs[k + m + i]); }
+};
+
+// As encode_columns, for K = k blocks and the rows of `rows`; one block is
+// loaded ahead of the one being XORed in.
+template <int M, bool FULL, class Blocks>
+__device__ __forceinline__ void encode_columns_rt(const Blocks &src, int k, const BitRows &rows,
+                                                  uint64_t s0, uint64_t s1, uint64_t lim) {
+  uint32_t par[M][8];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) par[i][b] = 0;
+  uint32_t x[8], y[8];
+  load16<FULL>(src.data(0), s0, lim, x);
+  load16<FULL>(src.data(0), s1, lim, x + 4);
+  auto step = [&](uint32_t (&cur)[8], uint32_t (&nxt)[8], int j) {
+    if (j + 1 < k) {
+      load16<FULL>(src.data(j + 1), s0, lim, nxt);
+      load16<FULL>(src.data(j + 1), s1, lim, nxt + 4);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    bit_transpose(cur);
+    // the planes are materialised once (left free, the compiler folds the
+    // transpose's last step into every one of their 8 * M uses)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) asm volatile("" : "+v"(cur[b]));
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      uint64_t row8;   // the 8 rows of c_ij, row b in byte b
+      __builtin_memcpy(&row8, rows.r[j][i], 8);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint32_t row = (uint32_t)(row8 >> (8 * b)) & 0xFFu;
+        uint32_t acc = par[i][b];
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)   // acc ^ (plane & mask), truth table 0x78
+          acc = __builtin_amdgcn_bitop3_b32(acc, cur[bi], 0u - ((row >> bi) & 1u), 0x78);
+        par[i][b] = acc;
+        asm volatile("" : "+v"(par[i][b]));
+      }
+    }
+  };
+  for (int j = 0; j < k; j += 2) {
+    step(x, y, j);
+    if (j + 1 < k) step(y, x, j + 1);
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    bit_transpose(par[i]);
+    store16<FULL>(src.parity(i), s0, lim, par[i]);
+    store16<FULL>(src.parity(i), s1, lim, par[i] + 4);
+  }
+}
+
+template <int M, class Blocks>
+__device__ __forceinline__ void encode_chunk_rt(const Blocks &src, int k, const BitRows &rows,
+                                                uint64_t c, uint64_t lim, uint32_t lane) {
+  const uint64_t s0 = c + 16 * lane, s1 = s0 + 1024;
+  if (c + kWaveCols <= lim)
+    encode_columns_rt<M, true>(src, k, rows, s0, s1, lim);
+  else
+    encode_columns_rt<M, false>(src, k, rows, s0, s1, lim);
+}
+
+template <int M>
+__global__ void __launch_bounds__(kBitmatrixThreads)
+__attribute__((amdgpu_waves_per_eu(bitmatrix_waves_per_eu<M>()))) bitmatrix_rt_kernel(
+    BitmatrixRtParams p) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBitmatrixThreads + threadIdx.x) >> 6;
+  const uint64_t c = wave * kWaveCols;
+  if (c >= p.io.block_bytes) return;
+  encode_chunk_rt<M>(ArgBlocks{p.io}, p.k, p.rows, c, p.io.block_bytes, threadIdx.x & 63);
+}
+
+template <int M>
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(4))) bitmatrix_rt_batch_kernel(BitmatrixRtBatch a) {
+  batch_tiles(a.g, [&](const_as<uint64_t> ptrs, uint64_t cc, uint64_t c1, uint32_t lane) {
+    encode_chunk_rt<M>(TableBlocksRt{ptrs, a.k, M}, a.k, a.rows, cc, c1, lane);
+  });
 }
 
 using BitmatrixFn = void (*)(BitmatrixParams);
@@ -364,33 +484,79 @@ BitmatrixKernels pick_bitmatrix(int k, int m) {
   return {nullptr, nullptr};
 }
 
+using BitmatrixRtFn = void (*)(BitmatrixRtParams);
+using BitmatrixRtBatchFn = void (*)(BitmatrixRtBatch);
+
+template <int M>
+constexpr std::pair<BitmatrixRtFn, BitmatrixRtBatchFn> rt_pair() {
+  return {bitmatrix_rt_kernel<M>, bitmatrix_rt_batch_kernel<M>};
+}
+
+std::pair<BitmatrixRtFn, BitmatrixRtBatchFn> pick_rt(int m) {
+  switch (m) {
+    case 1: return rt_pair<1>();
+    case 2: return rt_pair<2>();
+    case 3: return rt_pair<3>();
+    case 4: return rt_pair<4>();
+    case 5: return rt_pair<5>();
+    case 6: return rt_pair<6>();
+    case 7: return rt_pair<7>();
+    case 8: return rt_pair<8>();
+    default: return {nullptr, nullptr};
+  }
+}
+
+bool valid_code(const BitmatrixCode &bc) {
+  return bc.k >= 1 && bc.k <= kBitmatrixMaxK && bc.m >= 1 && bc.m <= kMaxM &&
+         (bc.builtin ? pick_bitmatrix(bc.k, bc.m).plain != nullptr : bc.rows != nullptr);
+}
+
 }  // namespace
 
-bool bitmatrix_supported(int k, int m, int w, unsigned poly) {
+bool bitmatrix_builtin(int k, int m, int w, unsigned poly) {
   return w == 8 && poly == kPoly && pick_bitmatrix(k, m).plain != nullptr;
 }
 
-int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *parity,
-                     uint64_t offset, uint64_t block_bytes, void *stream) {
-  const BitmatrixFn fn = pick_bitmatrix(k, m).plain;
-  if (!fn || block_bytes == 0 || block_bytes > kMaxPieceBytes) return (int)hipErrorInvalidValue;
+int launch_bitmatrix(const BitmatrixCode &bc, const uint8_t *const *data,
+                     uint8_t *const *parity, uint64_t offset, uint64_t block_bytes,
+                     void *stream) {
+  if (!valid_code(bc) || block_bytes == 0 || block_bytes > kMaxPieceBytes)
+    return (int)hipErrorInvalidValue;
   BitmatrixParams p{};
-  for (int j = 0; j < k; ++j) p.data[j] = data[j] + offset;
-  for (int i = 0; i < m; ++i) p.parity[i] = parity[i] + offset;
+  for (int j = 0; j < bc.k; ++j) p.data[j] = data[j] + offset;
+  for (int i = 0; i < bc.m; ++i) p.parity[i] = parity[i] + offset;
   p.block_bytes = block_bytes;
   const uint64_t waves = (block_bytes + kWaveCols - 1) / kWaveCols;
   const uint64_t wgs = (waves + kBitmatrixThreads / 64 - 1) / (kBitmatrixThreads / 64);
-  hipLaunchKernelGGL(fn, dim3((uint32_t)wgs), dim3(kBitmatrixThreads), 0,
-                     (hipStream_t)stream, p);
+  if (bc.builtin) {
+    hipLaunchKernelGGL(pick_bitmatrix(bc.k, bc.m).plain, dim3((uint32_t)wgs),
+                       dim3(kBitmatrixThreads), 0, (hipStream_t)stream, p);
+  } else {
+    BitmatrixRtParams rp{};
+    rp.io = p;
+    rp.k = bc.k;
+    rp.rows = *bc.rows;
+    hipLaunchKernelGGL(pick_rt(bc.m).first, dim3((uint32_t)wgs), dim3(kBitmatrixThreads), 0,
+                       (hipStream_t)stream, rp);
+  }
   return (int)hipGetLastError();
 }
 
-int launch_bitmatrix_batch(int k, int m, const BatchGroup &g, int grid, int threads,
+int launch_bitmatrix_batch(const BitmatrixCode &bc, const BatchGroup &g, int grid, int threads,
                            void *stream) {
-  const BitmatrixBatchFn fn = pick_bitmatrix(k, m).batch;
-  if (!fn || threads < 64 || threads > 1024 || threads % 64 || grid < 1)
+  if (!valid_code(bc) || threads < 64 || threads > 1024 || threads % 64 || grid < 1)
     return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, (hipStream_t)stream, g);
+  if (bc.builtin) {
+    hipLaunchKernelGGL(pick_bitmatrix(bc.k, bc.m).batch, dim3(grid), dim3(threads), 0,
+                       (hipStream_t)stream, g);
+  } else {
+    BitmatrixRtBatch a{};
+    a.g = g;
+    a.k = bc.k;
+    a.rows = *bc.rows;
+    hipLaunchKernelGGL(pick_rt(bc.m).second, dim3(grid), dim3(threads), 0, (hipStream_t)stream,
+                       a);
+  }
   return (int)hipGetLastError();
 }
 

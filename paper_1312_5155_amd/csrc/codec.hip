@@ -1179,7 +1179,7 @@ int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
                      0, st, g);
   int err = (int)hipGetLastError();
   if (err) return err;
-  if (cfg.bm_k) return launch_bitmatrix_batch(cfg.bm_k, cfg.bm_m, g, cfg.grid, cfg.threads, st);
+  if (cfg.bm) return launch_bitmatrix_batch(*cfg.bm, g, cfg.grid, cfg.threads, st);
   const int w = cfg.dwords_per_lane;
   BatchFn fn;
   // (the matrix-form update has no LFSR tables: the placement does not apply)

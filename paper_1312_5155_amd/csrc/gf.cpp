@@ -117,6 +117,28 @@ int Code::init(int k, int m, int w, unsigned poly) {
     for (int i = m - 1; i >= 1; --i) r[i] = r[i - 1] ^ F_.mul(top, g_[i]);
     r[0] = F_.mul(top, g_[0]);
   }
+
+  // Bit-sliced form (k <= kBitmatrixMaxK): row b of the product by c_ij has
+  // bit b' set when bit b of c_ij * 2^b' is.
+  bm_ = BitmatrixCode{};
+  if (k <= kBitmatrixMaxK) {
+    bm_rows_ = std::make_unique<BitRows>();
+    memset(bm_rows_.get(), 0, sizeof(BitRows));
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < m; ++i) {
+        const uint8_t c = pcol_[(size_t)j * m + i];
+        for (int bi = 0; bi < w; ++bi) {
+          const uint8_t prod = F_.mul(c, (uint8_t)(1u << bi));
+          for (int b = 0; b < w; ++b)
+            if ((prod >> b) & 1) bm_rows_->r[j][i][b] |= (uint8_t)(1u << bi);
+        }
+      }
+    bm_.k = k;
+    bm_.m = m;
+    bm_.builtin = bitmatrix_builtin(k, m, w, poly);
+    bm_.rows = bm_rows_.get();
+    bm_.key = (int)(poly << 12) | (k << 4) | m;
+  }
   return RS_OK;
 }
 

@@ -75,6 +75,8 @@ class Code {
   // The m coefficients of x^(m+j) mod g(x), low degree first (column j of
   // the generator matrix, Sec. 6).
   const uint8_t *column(int j) const { return &pcol_[(size_t)j * m_]; }
+  // The bit-sliced form of the code (k <= kBitmatrixMaxK), else nullptr.
+  const BitmatrixCode *bitmatrix() const { return bm_rows_ ? &bm_ : nullptr; }
   // Plan for the erasure list e[0..t), validated and sorted increasingly by
   // the caller; rebuilt symbol i is block e[i].  Cached (Opt3 of Sec. 4).
   std::shared_ptr<const DecodePlan> plan(const int *e, int t, unsigned flags);
@@ -87,6 +89,8 @@ class Code {
   uint8_t g_[kMaxM + 1] = {};
   uint32_t lfsr_basis_[16] = {};
   std::vector<uint8_t> pcol_;   // k x m: row j = coefficients of x^(m+j) mod g
+  std::unique_ptr<BitRows> bm_rows_;
+  BitmatrixCode bm_;
 
   // LRU cache of plans keyed by (erased-block bitmap, flags).
   struct Key {

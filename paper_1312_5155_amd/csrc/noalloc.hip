@@ -113,8 +113,7 @@ extern "C" int rs_poly_batch_noalloc(int op, const rs_poly_stripe_t *stripes, in
     lc.threads = launch[w].threads;
     lc.grid = ncu * launch[w].wgs_per_cu;
     lc.nibble = launch[w].table_placement == RS_POLY_TABLES_NIBBLE;
-    lc.bm_k = gp.bm_k;
-    lc.bm_m = gp.bm_m;
+    lc.bm = gp.bm;
     const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
                       : op == RS_POLY_OP_UPDATE ? (gp.matrix ? kUpdateMatrix : kUpdate)
                                                 : kEncode;

@@ -71,6 +71,8 @@ struct CodecParams {
 enum Mode : int { kEncode = 0, kDecode = 1, kUpdate = 2, kUpdateMatrix = 3, kUpdateMatrixWide = 11 };
 constexpr int kMatrixMaxBlocks = 8;
 
+struct BitmatrixCode;
+
 // A launch configuration of the codec kernel.
 struct LaunchCfg {
   int dwords_per_lane;   // 1, 2 or 4: bytes per lane per block = 4x this
@@ -78,16 +80,31 @@ struct LaunchCfg {
   int grid;              // workgroups; 0 = pick from the size
   bool bytewise;         // byte loads/stores (for misaligned blocks)
   bool nibble;           // batch kernels: split-nibble LFSR tables
-  int bm_k = 0, bm_m = 0;  // batch encode: the bit-sliced kernel of RS(bm_k, bm_m)
+  const BitmatrixCode *bm = nullptr;   // batch encode: bit-sliced, of this code
 };
 
 // Launches the codec kernel for one stripe.  Returns a hipError_t as int.
 int launch_codec(Mode mode, int state_bytes, const CodecParams &p,
                  const LaunchCfg &cfg, void *stream);
 
-// Largest k of the bit-sliced encode's codes; whether a code is built in.
+// Bit-sliced encode of one code.  rows.r[j][i][b] has bit b' set when bit
+// b of c_ij * 2^b' is, c_ij the coefficient of x^i in x^(m+j) mod g(x)
+// (the product by c_ij as an 8 x 8 matrix over GF(2), row b); for w = 4
+// the rows and bits from 4 up are zero.  `builtin`: the code's XOR network
+// is compiled in (GF(2^8), polynomial 0x11D, a few (k, m)); otherwise the
+// kernel takes the rows at run time.  `key` tells codes apart for cached
+// launches: field polynomial, k and m.
 constexpr int kBitmatrixMaxK = 32;
-bool bitmatrix_supported(int k, int m, int w, unsigned poly);
+struct BitRows {
+  uint8_t r[kBitmatrixMaxK][kMaxM][8];
+};
+struct BitmatrixCode {
+  int k = 0, m = 0;
+  bool builtin = false;
+  const BitRows *rows = nullptr;
+  int key = 0;
+};
+bool bitmatrix_builtin(int k, int m, int w, unsigned poly);
 
 // ------------------------------------------------------------- batches --
 //
@@ -139,16 +156,17 @@ const uint8_t *device_zero_page();
 int launch_batch(Mode mode, int state_bytes, const BatchGroup &g, uint64_t max_tiles,
                  const LaunchCfg &cfg, void *stream, bool pull = true);
 
-// Bit-sliced encode (bitmatrix.hip): compiled in for a few codes over
-// GF(2^8) with polynomial 0x11D; blocks 16-byte aligned.  launch_bitmatrix
-// encodes columns [offset, offset + block_bytes) (block_bytes <=
-// kMaxPieceBytes); launch_bitmatrix_batch launches the persistent batch
-// kernel for a group of RS(k, m) encode stripes whose tile_cols is a
-// multiple of kBitmatrixTileCols (after the pull and prepare kernels).
-// Both return a hipError_t as int.
-int launch_bitmatrix(int k, int m, const uint8_t *const *data, uint8_t *const *parity,
-                     uint64_t offset, uint64_t block_bytes, void *stream);
-int launch_bitmatrix_batch(int k, int m, const BatchGroup &g, int grid, int threads,
+// Bit-sliced encode (bitmatrix.hip) of any code with k <= kBitmatrixMaxK;
+// blocks 16-byte aligned.  launch_bitmatrix encodes columns [offset,
+// offset + block_bytes) (block_bytes <= kMaxPieceBytes);
+// launch_bitmatrix_batch launches the persistent batch kernel for a group
+// of encode stripes of that one code whose tile_cols is a multiple of
+// kBitmatrixTileCols (after the pull and prepare kernels).  Both return a
+// hipError_t as int.
+int launch_bitmatrix(const BitmatrixCode &bc, const uint8_t *const *data,
+                     uint8_t *const *parity, uint64_t offset, uint64_t block_bytes,
+                     void *stream);
+int launch_bitmatrix_batch(const BitmatrixCode &bc, const BatchGroup &g, int grid, int threads,
                            void *stream);
 constexpr uint32_t kBitmatrixTileCols = 2048;
 

@@ -107,7 +107,7 @@ def test_validation_happens_before_any_device_call():
     assert lib.rs_poly_encode(h, None, p, 16, None) == B.RS_ENULL
     p[2] = None
     assert lib.rs_poly_encode(h, d, p, 16, None) == B.RS_ENULL
-    # bit-matrix encode: built-in codes only, 16-byte aligned pointers
+    # bit-matrix encode: k <= 32, 16-byte aligned pointers
     p3 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
     enc_bm = lib.rs_poly_encode_bitmatrix
     assert enc_bm(h, d, p3, 0, None) == B.RS_OK                    # empty: no-op
@@ -115,12 +115,17 @@ def test_validation_happens_before_any_device_call():
     assert enc_bm(None, d, p3, 16, None) == B.RS_ENULL
     d_odd = (ctypes.c_void_p * 10)(*([0x1000] * 9 + [0x1008]))
     assert enc_bm(h, d_odd, p3, 16, None) == B.RS_EINVAL            # 8-byte aligned
-    h93 = B.Code(9, 3)
-    assert enc_bm(h93.handle, d, p3, 16, None) == B.RS_EINVAL       # not built in
-    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x11D) == 1
+    h33b = B.Code(33, 4)
+    d33b = (ctypes.c_void_p * 33)(*([0x1000] * 33))
+    assert enc_bm(h33b.handle, d33b, p3, 16, None) == B.RS_EINVAL   # k = 33 > 32
+    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x11D) == 1   # compiled in
     assert lib.rs_poly_bitmatrix_supported(32, 8, 8, 0x11D) == 1
-    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x12B) == 0
-    assert lib.rs_poly_bitmatrix_supported(4, 3, 4, 0x13) == 0
+    assert lib.rs_poly_bitmatrix_supported(9, 3, 8, 0x11D) == 1    # run-time rows
+    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x12B) == 1
+    assert lib.rs_poly_bitmatrix_supported(4, 3, 4, 0x13) == 1
+    assert lib.rs_poly_bitmatrix_supported(33, 4, 8, 0x11D) == 0   # k > 32
+    assert lib.rs_poly_bitmatrix_supported(10, 4, 8, 0x11B) == 0   # not a code
+    assert lib.rs_poly_bitmatrix_supported(12, 4, 4, 0x13) == 0
     # generator-matrix encode: k <= 32
     enc_mx = lib.rs_poly_encode_matrix
     h6 = B.Code(6, 3)

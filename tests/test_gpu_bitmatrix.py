@@ -1,7 +1,9 @@
 """GPU parity of the bit-sliced (XOR-only) encode against the oracle, byte
-for byte, through the C ABI: every code built in, sizes that span several
-2048-column wave chunks with ragged tails (bytes past the blocks left
-untouched), and agreement with the LFSR encode at full workload sizes."""
+for byte, through the C ABI: every code whose XOR network is compiled in
+and codes that take their matrices at run time (other k and m, another
+GF(2^8) polynomial, GF(2^4)), sizes that span several 2048-column wave
+chunks with ragged tails (bytes past the blocks left untouched), and
+agreement with the LFSR encode at full workload sizes."""
 import sys
 
 import numpy as np
@@ -16,6 +18,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 BUILT_IN = [(6, 3), (10, 4), (12, 4), (32, 8)]
+# (k, m, w, poly): codes whose matrices the kernel takes at run time
+RUNTIME = [(9, 4, 8, 0x11D), (1, 1, 8, 0x11D), (5, 8, 8, 0x11D), (20, 6, 8, 0x11D),
+           (32, 7, 8, 0x11D), (3, 2, 8, 0x11D), (10, 4, 8, 0x12B), (16, 5, 8, 0x187),
+           (4, 3, 4, 0x13), (9, 5, 4, 0x13), (13, 2, 4, 0x19)]
 SIZES = [1, 15, 16, 17, 1000, 2047, 2048, 2049, 4096 + 100, 3 * 65536 + 5]
 
 
@@ -46,8 +52,21 @@ def bitmatrix_encode(code, data_np):
 def test_supported_codes():
     for k, m in BUILT_IN:
         assert B.rs_poly_bitmatrix_supported(k, m)
-    assert not B.rs_poly_bitmatrix_supported(9, 4)
-    assert not B.rs_poly_bitmatrix_supported(4, 3, 4, 0x13)
+    for k, m, w, poly in RUNTIME:
+        assert B.rs_poly_bitmatrix_supported(k, m, w, poly)
+    assert not B.rs_poly_bitmatrix_supported(33, 4)
+
+
+@pytest.mark.parametrize("k,m,w,poly", RUNTIME)
+def test_runtime_bitmatrix_encode_matches_oracle(k, m, w, poly):
+    code = B.Code(k, m, w, poly)
+    F = oracle.Field(w, poly)
+    for i, Bn in enumerate(SIZES):
+        say(f"bit-matrix (run-time rows) RS({k},{m}) GF(2^{w}) poly {poly:#x} B={Bn}")
+        data = workloads.random_bytes(3000 * k + 7 * m + i, (k, Bn)) & ((1 << w) - 1)
+        par, guards = bitmatrix_encode(code, data)
+        assert np.array_equal(par, oracle.encode(F, k, m, data)), (k, m, w, Bn)
+        assert guards, (k, m, w, Bn)
 
 
 @pytest.mark.parametrize("k,m", BUILT_IN)
@@ -77,7 +96,8 @@ def test_bitmatrix_unit_data_gives_generator_columns():
     assert not par[:, np.setdiff1d(np.arange(Bn), 64 * np.arange(k) + 3)].any()
 
 
-@pytest.mark.parametrize("k,m,Bn", [(10, 4, 64 << 20), (32, 8, (16 << 20) + 48)])
+@pytest.mark.parametrize("k,m,Bn", [(10, 4, 64 << 20), (32, 8, (16 << 20) + 48),
+                                    (16, 4, (32 << 20) + 48)])
 def test_bitmatrix_full_size_agrees_with_lfsr_encode(k, m, Bn):
     say(f"bit-matrix vs LFSR RS({k},{m}) B={Bn}")
     code = B.Code(k, m)
@@ -133,6 +153,20 @@ def test_batched_bitmatrix_matches_oracle(k, m, threads, tile, order):
     bpl = 4 if threads == 1024 else 16 if m <= 4 else 8
     launch = {"bytes_per_lane": bpl, "threads": threads, "tile_bytes": tile,
               "wgs_per_cu": 2, "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": order}
+    for par, d in zip(batch_encode(data, codes, launch), data):
+        assert np.array_equal(par, oracle.encode(F, k, m, d))
+
+
+@pytest.mark.parametrize("k,m,w,poly", [(9, 4, 8, 0x11D), (20, 6, 8, 0x11D), (7, 3, 4, 0x13)])
+def test_batched_runtime_bitmatrix_matches_oracle(k, m, w, poly):
+    say(f"batched bit-matrix (run-time rows) RS({k},{m}) GF(2^{w})")
+    F = oracle.Field(w, poly)
+    sizes = [1, 4095, 2048, 70001, 3 * 2048 + 17, 200000]
+    data = [workloads.random_bytes(91 * k + i, (k, n)) & ((1 << w) - 1)
+            for i, n in enumerate(sizes)]
+    codes = [B.Code(k, m, w, poly)] * len(sizes)
+    launch = {"bytes_per_lane": 16 if m <= 4 else 8, "threads": 512, "tile_bytes": 16384,
+              "wgs_per_cu": 2, "table_placement": B.RS_POLY_TABLES_BITMATRIX, "tile_order": 1}
     for par, d in zip(batch_encode(data, codes, launch), data):
         assert np.array_equal(par, oracle.encode(F, k, m, d))
 
