@@ -777,6 +777,8 @@ def main():
                     help="FETCH, WRITE, calibration FETCH, calibration WRITE "
                          "counter_collection.csv files -> profiles/ traffic JSON")
     ap.add_argument("--traffic-workload", default=HEADLINE, choices=WORKLOADS)
+    ap.add_argument("--leg", choices=("plain_encoders", "plain_update_forms"),
+                    help="only this one-stripe leg (for profiling its kernels)")
     args = ap.parse_args()
     loads = [0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.2]
 
@@ -789,6 +791,13 @@ def main():
     if args.serving_sweep:
         res = serving(loads, max(1, args.serving_requests))
         print(json.dumps({"workload": "serving_rs104", **res}), flush=True)
+        return
+    if args.leg:
+        import torch
+        legs = {"plain_encoders": plain_encoders_leg, "plain_update_forms": nibble_update_leg}
+        res = legs[args.leg](torch.device("cuda:0"), torch.cuda.current_stream(),
+                             max(1, args.encoder_steps))
+        print(json.dumps({"leg": args.leg, **res}), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
