@@ -636,14 +636,18 @@ __device__ __forceinline__ void matrix_lookups(uint32_t d0, uint32_t d1, uint32_
 // out: they are the leading window positions of the first group that hold
 // no block (padding or absent blocks above every present one), where the
 // state is still zero, so the feedback is zero and a step changes nothing.
-// A matrix-update item adds its blocks' packed products instead.
-template <int M, int W, int MODE>
-__device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
-                                           bool data_item, int g, const uint8_t *lds,
-                                           const Lanes<M, MODE> &t) {
+// A matrix-update item adds its blocks' packed products instead.  DATA:
+// the item is a data group (else the parity item); a template argument, so
+// that the rotation of data groups is code of its own rather than a
+// per-column select between rotated and unrotated words.
+template <int M, int W, int MODE, bool DATA>
+__device__ __forceinline__ void absorb_xor_item(uint32_t (&s)[4 * W][M / 4],
+                                                const uint32_t (&a)[M][W], int g,
+                                                const uint8_t *lds, const Lanes<M, MODE> &t) {
   constexpr int NQ = M / 4;
   constexpr bool kMatrix = op_of(MODE) == kUpdateMatrix;
-  const bool lfsr = data_item && !kMatrix;
+  constexpr bool data_item = DATA;
+  constexpr bool lfsr = DATA && !kMatrix;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     uint32_t d[NQ][4];
@@ -659,7 +663,7 @@ __device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const ui
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       if constexpr (kMatrix) {
-        if (data_item) {
+        if constexpr (data_item) {
           uint32_t acc[NQ];
 #pragma unroll
           for (int h = 0; h < NQ; ++h) acc[h] = 0;
@@ -685,7 +689,7 @@ __device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const ui
           for (int h = 0; h < NQ; ++h) d[h][x] = acc[h];
         }
       } else if constexpr (M == 8) {
-        if (lfsr) {
+        if constexpr (lfsr) {
           const uint32_t lo = perm(d[1][x], d[0][x], t.rin[0]);
           const uint32_t hi = perm(d[1][x], d[0][x], t.rin[1]);
           d[0][x] = lo;
@@ -696,6 +700,16 @@ __device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const ui
       for (int h = 0; h < NQ; ++h) s[4 * w + x][h] ^= d[h][x];
     }
   }
+}
+
+template <int M, int W, int MODE>
+__device__ __forceinline__ void absorb_xor(uint32_t (&s)[4 * W][M / 4], const uint32_t (&a)[M][W],
+                                           bool data_item, int g, const uint8_t *lds,
+                                           const Lanes<M, MODE> &t) {
+  if (op_of(MODE) == kEncode || data_item)   // an encode has no parity item
+    absorb_xor_item<M, W, MODE, true>(s, a, g, lds, t);
+  else
+    absorb_xor_item<M, W, MODE, false>(s, a, g, lds, t);
 }
 
 // The M LFSR steps of a data item (after absorb_xor), less the first `skip`.
