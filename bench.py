@@ -850,7 +850,7 @@ def main():
         for name in WORKLOADS:
             if name == args.workload:
                 continue
-            rec = run_batched(name, args, dev, stream, src_hash)
+            rec = run_batched(name, args, dev, stream, src_hash, roofline=True)
             b2, s2, e2, v2, c2, bt2, enc2 = rec.pop("_state")
             if name == "rs104_256x1MiB":
                 if args.update_steps > 0:

@@ -111,3 +111,36 @@ def test_bitmatrix_encode_over_2GiB():
         assert np.array_equal(rows[k + m:k + 2 * m, lo:hi].cpu().numpy(), oracle.encode(F, k, m, d))
     del rows
     torch.cuda.empty_cache()
+
+
+def test_nibble_update_over_2GiB():
+    # The split-nibble update walks blocks of any size in one launch (64-bit
+    # chunk indices): 2 changed blocks of RS(3,2) with blocks over 2 GiB.  The
+    # result equals the LDS update of the same delta from the same parity,
+    # and on windows the parity change equals the oracle's encoding of the
+    # delta.
+    k, m = 3, 2
+    say(f"nibble update RS({k},{m}) blocks of {NB} bytes")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.data_seed(11))
+    delta = torch.zeros((k, NBP), dtype=torch.uint8, device="cuda")
+    for j in (0, 2):
+        delta[j, :NB] = torch.randint(0, 256, (NB,), dtype=torch.uint8, device="cuda",
+                                      generator=gen)
+    par = torch.randint(0, 256, (2 * m, NBP), dtype=torch.uint8, device="cuda", generator=gen)
+    par[m:] = par[:m]
+    before = {w: par[:m, w[0]:w[1]].cpu().numpy() for w in WINDOWS}
+    code = B.Code(k, m)
+    dptr = [delta[0].data_ptr(), None, delta[2].data_ptr()]
+    code.update_nibble(dptr, [par[i].data_ptr() for i in range(m)], NB)
+    code.update(dptr, [par[m + i].data_ptr() for i in range(m)], NB)
+    torch.cuda.synchronize()
+    assert torch.equal(par[:m, :NB], par[m:, :NB])
+    assert torch.equal(par[:m, NB:], par[m:, NB:])     # bytes past the blocks untouched
+    F = oracle.Field(8, 0x11D)
+    for w in WINDOWS:
+        d = delta[:, w[0]:w[1]].cpu().numpy()
+        want = before[w] ^ oracle.encode(F, k, m, d)
+        assert np.array_equal(par[:m, w[0]:w[1]].cpu().numpy(), want), w
+    del delta, par
+    torch.cuda.empty_cache()
