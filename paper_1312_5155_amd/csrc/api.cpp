@@ -69,7 +69,10 @@ LaunchCfg default_cfg(Mode mode, int sb, uint64_t B, int min_align, int num_cu) 
     while (w > 1 && (B + 4 * w - 1) / (4 * w) < want_lanes) w /= 2;
     cfg.dwords_per_lane = w;
   }
-  cfg.threads = std::min(512, codec_max_threads(mode, sb, cfg.dwords_per_lane));
+  // Wide codes: 1024 threads, so that the decode (one workgroup per CU for
+  // its 128 KiB of tables) still has four waves per SIMD.
+  const int tmax = codec_max_threads(mode, sb, cfg.dwords_per_lane);
+  cfg.threads = sb == 8 ? tmax : std::min(512, tmax);
   const uint64_t cols = 4ull * cfg.dwords_per_lane;
   const uint64_t chunks = (B + cols - 1) / cols;
   const uint64_t wgs = (chunks + cfg.threads - 1) / cfg.threads;

@@ -1135,8 +1135,7 @@ KernelFn pick(int sb, int w, bool bytewise) {
     if (w == 2) return codec_kernel<4, 2, MODE, false>;
     return codec_kernel<4, 1, MODE, false>;
   }
-  // (no 16-byte variant for wide codes: its arguments would be copied to
-  // scratch for dynamic indexing)
+  if (w == 4) return codec_kernel<8, 4, MODE, false>;
   if (w >= 2) return codec_kernel<8, 2, MODE, false>;
   return codec_kernel<8, 1, MODE, false>;
 }
@@ -1157,7 +1156,7 @@ BatchFn pick_batch(int sb, int w) {
 
 int codec_wgs_per_cu(Mode) { return 2; }
 
-int codec_plain_max_dwords(int sb) { return sb == 8 ? 2 : 4; }
+int codec_plain_max_dwords(int) { return 4; }
 
 int codec_max_threads(Mode mode, int sb, int dwords_per_lane) {
   return dwords_per_lane == 4 && sb == 4 ? 512 : 1024;

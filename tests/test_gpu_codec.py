@@ -191,3 +191,36 @@ def test_repeat_runs_are_identical():
     a, _, _ = gpu_encode(code, data)
     b, _, _ = gpu_encode(code, data)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("k,m,Bn", [(32, 8, (16 << 20) + 48), (20, 6, (8 << 20) + 4),
+                                    (10, 4, (8 << 20) + 12)])
+def test_plain_large_aligned_blocks(k, m, Bn):
+    # Blocks on a 256-byte-padded stride (16-byte aligned) and large enough
+    # for the widest plain variant (16 bytes per lane; 1024 threads for the
+    # wide codes), with a ragged length: the encode matches the oracle on
+    # column windows at both ends and in the middle, and the decode of m
+    # erased blocks (data and parity) restores them exactly.
+    say(f"plain large RS({k},{m}) B={Bn}")
+    code = B.Code(k, m)
+    stride = (Bn + 255) // 256 * 256
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.data_seed(6) + k)
+    buf = torch.zeros((k + m, stride), dtype=torch.uint8, device="cuda")
+    buf[:k] = torch.randint(0, 256, (k, stride), dtype=torch.uint8, device="cuda", generator=gen)
+    assert buf[1].data_ptr() % 16 == 0
+    code.encode(rows(buf[:k]), rows(buf[k:]), Bn)
+    torch.cuda.synchronize()
+    F = field()
+    for c0 in (0, Bn // 2 - 333, Bn - 40000):
+        w = (c0, c0 + 40000)
+        want = oracle.encode(F, k, m, buf[:k, w[0]:w[1]].cpu().numpy())
+        assert np.array_equal(buf[k:, w[0]:w[1]].cpu().numpy(), want), (k, m, c0)
+    assert not buf[k:, Bn:].any()                     # nothing past the blocks
+    rng = workloads.meta_rng(k * 7 + m)
+    er = workloads.random_erasures(rng, k + m, m)
+    saved = buf[er].clone()
+    buf[er] = 0x6B
+    code.decode(rows(buf), er, Bn)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[er, :Bn], saved[:, :Bn]), er
