@@ -7,10 +7,12 @@
 // The coefficients depend only on (k, m) and the field, so for the codes
 // compiled in here they are compile-time constants and the whole XOR
 // network unrolls into straight-line code: no tables, no LDS, no serial
-// LFSR chain.  Each lane takes 32 byte columns (two 16-byte runs 1 KiB
-// apart, so every load instruction of a wave is one contiguous 1 KiB),
-// bit-transposes each block's 32 bytes into 8 planes of 32 bits, XORs the
-// planes into the m x 8 parity planes, and transposes those back.
+// LFSR chain.  Any other code (k <= kBitmatrixMaxK, either field) takes its
+// GF(2) rows with the launch and applies each row as masked XORs.  Each
+// lane takes 32 byte columns (two 16-byte runs 1 KiB apart, so every load
+// instruction of a wave is one contiguous 1 KiB), bit-transposes each
+// block's 32 bytes into 8 planes of 32 bits, XORs the planes into the
+// m x 8 parity planes, and transposes those back.
 #include <hip/hip_runtime.h>
 
 #include <utility>
