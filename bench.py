@@ -449,7 +449,10 @@ def cpu_baseline(view, stripes, erasures, window, n_stripes, threads, seed):
 def update_leg(view, stripes, codes, batch, stream, steps, dev):
     """Batched delta-parity update (Sec. 3.2 update property), one changed
     data block per stripe: reads the delta and the parity, writes the
-    parity.  An even number of runs leaves the parity as it was."""
+    parity.  An even number of runs leaves the parity as it was.  Timed in
+    the library's default placement (register split-nibble products, for
+    stripes changing at most 2 blocks) and with the packed placement (the
+    generator-matrix LDS tables); both must leave the same bytes."""
     import torch
 
     from paper_1312_5155_amd import binding as B
@@ -468,24 +471,42 @@ def update_leg(view, stripes, codes, batch, stream, steps, dev):
     upd = B.StripeArray(ents)
     n_upd = steps + (steps & 1)
     ref = view[:, k:].clone()
-    batch.update(upd, stream)
-    batch.update(upd, stream)
-    u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    u0.record(stream)
-    for _ in range(n_upd):
-        batch.update(upd, stream)
-    u1.record(stream)
-    torch.cuda.synchronize()
-    if not torch.equal(view[:, k:], ref):
-        raise SystemExit("an even number of updates changed the parity")
-    ms = u0.elapsed_time(u1) / n_upd
+    wide = 1 if m > 4 else 0
     alg = S * (1 + 2 * m) * nb
-    launch = batch.get_launch(B.RS_POLY_OP_UPDATE, 0).as_dict()
-    return {"avg_ms": round(ms, 4), "alg_bytes": alg, "gbs": round(alg / (ms / 1e3) / 1e9, 1),
-            "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "user_gbs": round(S * nb / (ms / 1e3) / 1e9, 1), "changed_blocks_per_stripe": 1,
-            "kernel": batch_variant(B.RS_POLY_OP_UPDATE, launch, m=m, matrix_update=True),
-            "launch": launch}
+
+    def timed():
+        batch.update(upd, stream)
+        batch.update(upd, stream)
+        u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        u0.record(stream)
+        for _ in range(n_upd):
+            batch.update(upd, stream)
+        u1.record(stream)
+        torch.cuda.synchronize()
+        if not torch.equal(view[:, k:], ref):
+            raise SystemExit("an even number of updates changed the parity")
+        return u0.elapsed_time(u1) / n_upd
+
+    ms = timed()
+    launch = batch.get_launch(B.RS_POLY_OP_UPDATE, wide).as_dict()
+    regs = launch["table_placement"] == B.RS_POLY_TABLES_REGISTERS
+    rec = {"avg_ms": round(ms, 4), "alg_bytes": alg, "gbs": round(alg / (ms / 1e3) / 1e9, 1),
+           "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "user_gbs": round(S * nb / (ms / 1e3) / 1e9, 1), "changed_blocks_per_stripe": 1,
+           "kernel": "nibble_batch_kernel" if regs else
+                     batch_variant(B.RS_POLY_OP_UPDATE, launch, m=m, matrix_update=True),
+           "launch": launch}
+    # the same updates in the generator-matrix form (packed LDS tables)
+    packed = dict(launch, table_placement=B.RS_POLY_TABLES_PACKED)
+    batch.set_launch(B.RS_POLY_OP_UPDATE, wide, packed)
+    ms_p = timed()
+    batch.set_launch(B.RS_POLY_OP_UPDATE, wide, launch)
+    rec["matrix_form"] = {"avg_ms": round(ms_p, 4), "gbs": round(alg / (ms_p / 1e3) / 1e9, 1),
+                          "frac": round(alg / (ms_p / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "kernel": batch_variant(B.RS_POLY_OP_UPDATE, packed, m=m,
+                                                  matrix_update=True),
+                          "launch": packed}
+    return rec
 
 
 def plain_encoders_leg(dev, stream, steps):
@@ -838,6 +859,9 @@ def main():
     extras = {}
     if args.extras and args.encoder_steps > 0 and view is not None:
         extras["encoder_forms"] = encoder_forms_leg(view, stripes, codes, stream, 3)
+    if args.extras and args.update_steps > 0 and view is not None:
+        extras["batch_update_" + args.workload] = update_leg(view, stripes, codes, batch, stream,
+                                                             args.update_steps, dev)
     del buf, view, stripes, erasures, batch
     torch.cuda.empty_cache()
 

@@ -276,7 +276,8 @@ typedef struct rs_poly_launch {
     int wgs_per_cu;       /* persistent workgroups per CU: 1 or 2              */
     int table_placement;  /* LFSR tables in LDS: RS_POLY_TABLES_PACKED or      *
                            * RS_POLY_TABLES_NIBBLE; encode also                *
-                           * RS_POLY_TABLES_BITMATRIX                          */
+                           * RS_POLY_TABLES_BITMATRIX, update also             *
+                           * RS_POLY_TABLES_REGISTERS (the update default)     */
     int tile_order;       /* 0: tiles handed out in order (the workgroups work *
                            * on neighbouring tiles); 1: each workgroup walks   *
                            * its own run of tiles (dynamic claims either way)  */
@@ -294,6 +295,13 @@ typedef struct rs_poly_launch {
  * the PACKED tables with the same launch shape).  Tiles are rounded down to
  * a multiple of 2048 columns; bytes_per_lane does not apply. */
 #define RS_POLY_TABLES_BITMATRIX 2
+/* Update only: the split-nibble products held in registers, the kernel of
+ * rs_poly_update_nibble, for a state width whose stripes in the call all
+ * change at most 2 blocks with (changed blocks) * m <= 8 (any other call
+ * runs the PACKED forms with the same launch shape).  No LDS; each thread
+ * takes 16 bytes of every block per pass, so bytes_per_lane does not
+ * apply.  The default placement of batched updates. */
+#define RS_POLY_TABLES_REGISTERS 3
 
 #define RS_POLY_OP_ENCODE 0
 #define RS_POLY_OP_DECODE 1

@@ -161,6 +161,7 @@ RS_POLY_OP_UPDATE = 2
 RS_POLY_TABLES_PACKED = 0
 RS_POLY_TABLES_NIBBLE = 1
 RS_POLY_TABLES_BITMATRIX = 2
+RS_POLY_TABLES_REGISTERS = 3
 
 
 def check(rc, where):

@@ -162,6 +162,26 @@ void fill_update_params(const Code &c, const uint8_t *const *delta, uint8_t *con
   memcpy(p->lfsr_basis, c.lfsr_basis(), sizeof(p->lfsr_basis));
 }
 
+// Per (changed block t, parity i) the two 16-entry tables of the constant
+// P[i][j], column j = which[t] of the generator matrix (Sec. 6): the
+// products by the low nibbles n and by the high nibbles n << 4, entry n in
+// byte n (zero for w = 4, whose symbols have no high nibble).
+void nibble_tables(const Code &c, const int *which, int changed, uint32_t (*out)[8]) {
+  const Field &f = c.field();
+  for (int t = 0; t < changed; ++t) {
+    const uint8_t *col = c.column(which[t]);
+    for (int i = 0; i < c.m(); ++i) {
+      uint8_t lo[16], hi[16];
+      for (int n = 0; n < 16; ++n) {
+        lo[n] = f.mul(col[i], (uint8_t)n);
+        hi[n] = f.w() == 8 ? f.mul(col[i], (uint8_t)(n << 4)) : 0;
+      }
+      memcpy(&out[t * c.m() + i][0], lo, 16);
+      memcpy(&out[t * c.m() + i][4], hi, 16);
+    }
+  }
+}
+
 void fill_decode_params(const Code &c, const DecodePlan &plan, uint8_t *const *blocks,
                         const int *sorted, int t, uint64_t offset, uint64_t B,
                         CodecParams *p) {
@@ -401,25 +421,10 @@ int rs_poly_update_nibble(rs_poly_t *h, const uint8_t *const *delta, uint8_t *co
   for (int i = 0; i < c.m(); ++i)
     if (pointer_alignment(parity[i]) < 16) return RS_EINVAL;
   if (block_bytes == 0) return RS_OK;
-  // Per (changed block t, parity i) the two 16-entry tables of the constant
-  // P[i][j], the column j of the generator matrix (Sec. 6): the products by
-  // the low nibbles n and by the high nibbles n << 4, entry n in byte n.
   NibbleParams p;
   memset(&p, 0, sizeof(p));
-  const Field &f = c.field();
-  for (int t = 0; t < changed; ++t) {
-    p.delta[t] = delta[which[t]];
-    const uint8_t *col = c.column(which[t]);
-    for (int i = 0; i < c.m(); ++i) {
-      uint8_t lo[16], hi[16];
-      for (int n = 0; n < 16; ++n) {
-        lo[n] = f.mul(col[i], (uint8_t)n);
-        hi[n] = f.w() == 8 ? f.mul(col[i], (uint8_t)(n << 4)) : 0;
-      }
-      memcpy(&p.tab[t * c.m() + i][0], lo, 16);
-      memcpy(&p.tab[t * c.m() + i][4], hi, 16);
-    }
-  }
+  nibble_tables(c, which, changed, p.tab);
+  for (int t = 0; t < changed; ++t) p.delta[t] = delta[which[t]];
   for (int i = 0; i < c.m(); ++i) p.parity[i] = parity[i];
   p.block_bytes = block_bytes;
   p.c = changed;

@@ -25,9 +25,10 @@ namespace rsp {
 namespace {
 
 constexpr int kOps = 3;     // encode, decode, update
-// Graph key of a batched update in the generator-matrix form (same launch
-// shape as RS_POLY_OP_UPDATE).
+// Graph keys of a batched update in the generator-matrix form and in the
+// register split-nibble form (same launch shape as RS_POLY_OP_UPDATE).
 constexpr int kOpUpdateMatrix = 3;
+constexpr int kOpUpdateNibble = 4;
 constexpr int kWidths = 2;  // state width 4 bytes (m <= 4), 8 bytes (m <= 8)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -74,7 +75,8 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
   if (c.threads > codec_max_threads(mode, wide ? 8 : 4, c.bytes_per_lane / 4)) return false;
   if (c.tile_bytes < 4096 || c.tile_bytes % 16 != 0) return false;
   if (c.table_placement != RS_POLY_TABLES_PACKED && c.table_placement != RS_POLY_TABLES_NIBBLE &&
-      !(c.table_placement == RS_POLY_TABLES_BITMATRIX && op == RS_POLY_OP_ENCODE))
+      !(c.table_placement == RS_POLY_TABLES_BITMATRIX && op == RS_POLY_OP_ENCODE) &&
+      !(c.table_placement == RS_POLY_TABLES_REGISTERS && op == RS_POLY_OP_UPDATE))
     return false;
   if (c.tile_order != 0 && c.tile_order != 1) return false;
   return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 2;
@@ -99,7 +101,10 @@ rs_poly_launch_t default_launch(int op, int wide) {
   }
   // (a wide decode workgroup takes 128 KiB of LDS: one fits per CU)
   c.wgs_per_cu = wide && op == RS_POLY_OP_DECODE ? 1 : 2;
-  c.table_placement = RS_POLY_TABLES_PACKED;
+  // Updates: the register split-nibble kernel when every stripe of a width
+  // changes at most 2 blocks (2-3% faster than the matrix form on the 1 MiB
+  // and 16 MiB workloads); any other update call runs the packed forms.
+  c.table_placement = op == RS_POLY_OP_UPDATE ? RS_POLY_TABLES_REGISTERS : RS_POLY_TABLES_PACKED;
   // RS(32,8) with 16 MiB blocks: the 40 blocks of a stripe sit 16 MiB apart,
   // and walking them at one column offset from every workgroup at once is
   // 8-9% slower for encode than giving each workgroup its own run of tiles
@@ -267,10 +272,12 @@ int rs_poly_batch::graph_for(int op, int wide, const rs_poly_launch_t &cfg, int 
   lc.bytewise = false;
   lc.nibble = cfg.table_placement == RS_POLY_TABLES_NIBBLE;
   lc.bm = bm;
+  lc.nibble_update = op == kOpUpdateNibble;
   GraphEntry e;
   const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
                     : op == RS_POLY_OP_UPDATE ? kUpdate
                     : op == kOpUpdateMatrix   ? kUpdateMatrix
+                    : op == kOpUpdateNibble   ? kUpdate
                                               : kEncode;
   int lerr = 0;
   hipError_t cerr = hipSuccess;
@@ -342,15 +349,23 @@ int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
   if (count > 0 && !stripes) return RS_ENULL;
   // Updates: a state width's stripes take the generator-matrix form when
   // none of them changes more than kMatrixMaxBlocks blocks.
+  // With the REGISTERS placement they take the register split-nibble
+  // kernel instead when every stripe changes few enough blocks.
   if (op == RS_POLY_OP_UPDATE) {
     plan[0].matrix = plan[1].matrix = true;
+    plan[0].nibble = launch[0].table_placement == RS_POLY_TABLES_REGISTERS;
+    plan[1].nibble = launch[1].table_placement == RS_POLY_TABLES_REGISTERS;
     for (int i = 0; i < count; ++i) {
       const rs_poly_stripe_t &st = stripes[i];
       if (!st.code || !st.blocks) continue;   // rejected below
       int which[kMatrixMaxBlocks];
-      if (update_changed(st.code->code, st.blocks, which) > kMatrixMaxBlocks)
-        plan[st.code->code.state_bytes() == 8].matrix = false;
+      const int n = update_changed(st.code->code, st.blocks, which);
+      GroupPlan &gp = plan[st.code->code.state_bytes() == 8];
+      if (n > kMatrixMaxBlocks) gp.matrix = false;
+      if (n > 0 && !nibble_supported(n, st.code->code.m())) gp.nibble = false;
     }
+    for (int w = 0; w < kWidths; ++w)
+      if (plan[w].nibble) plan[w].matrix = false;
   }
 
   // Encodes: a state width's stripes take the bit-sliced kernel when the
@@ -405,14 +420,19 @@ int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
     uint32_t aset = 0;
     int which[kMatrixMaxBlocks];
     const int changed = op == RS_POLY_OP_UPDATE ? update_changed(c, st.blocks, which) : 0;
-    if (gp.matrix) {
+    if (gp.matrix || gp.nibble) {
       GroupPlan::MatrixKey key{&c, 0, changed};
       for (int t = 0; t < changed; ++t) key.packed |= (uint64_t)which[t] << (8 * t);
       auto mi = gp.matrix_index.find(key);
       if (mi == gp.matrix_index.end()) {
         mi = gp.matrix_index.emplace(key, (uint32_t)(gp.apply.size() / (kMaxM * 16))).first;
+        // matrix form: the changed blocks' column bases; split-nibble
+        // form: their c * m nibble tables (at most 64 of the 128 dwords)
         uint32_t bases[kMaxM][16] = {};
-        for (int t = 0; t < changed; ++t) c.column_basis(which[t], bases[t]);
+        if (gp.nibble)
+          nibble_tables(c, which, changed, reinterpret_cast<uint32_t (*)[8]>(&bases[0][0]));
+        else
+          for (int t = 0; t < changed; ++t) c.column_basis(which[t], bases[t]);
         gp.apply.insert(gp.apply.end(), &bases[0][0], &bases[0][0] + kMaxM * 16);
       }
       aset = mi->second;
@@ -435,7 +455,7 @@ int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
       // the LFSR starts at block span - 1 (update: the highest changed
       // block; decode: the highest data block read); the matrix form reads
       // the changed blocks only
-      const int kk = gp.matrix ? changed : span;
+      const int kk = gp.matrix || gp.nibble ? changed : span;
       d.k = kk;
       d.m = m;
       d.k_pad = (kk + c.state_bytes() - 1) / c.state_bytes() * c.state_bytes();
@@ -450,7 +470,7 @@ int plan_batch(int op, const rs_poly_stripe_t *stripes, int count,
         for (int i2 = 0; i2 < m; ++i2) gp.ptrs.push_back(at(k + i2));
       } else if (op == RS_POLY_OP_UPDATE) {
         d.n_out = m;
-        if (gp.matrix)
+        if (gp.matrix || gp.nibble)
           for (int t = 0; t < changed; ++t) gp.ptrs.push_back(at(which[t]));
         else
           for (int j = 0; j < span; ++j) gp.ptrs.push_back(st.blocks[j] ? at(j) : 0);
@@ -555,7 +575,10 @@ int rs_poly_batch::run(int op, const rs_poly_stripe_t *stripes, int count, void 
   for (int w = 0; w < kWidths; ++w) {
     if (plan[w].descs.empty()) continue;
     hipGraphExec_t exec;
-    rc = graph_for(plan[w].matrix ? kOpUpdateMatrix : op, w, launch[op][w], si, plan[w].bm,
+    rc = graph_for(plan[w].nibble   ? kOpUpdateNibble
+                   : plan[w].matrix ? kOpUpdateMatrix
+                                    : op,
+                   w, launch[op][w], si, plan[w].bm,
                    &exec);
     if (rc != RS_OK) return rc;
     if (hipGraphLaunch(exec, st) != hipSuccess) return RS_EDEVICE;
@@ -757,12 +780,14 @@ int rs_poly_tune(rs_poly_batch_t *b, int op, const rs_poly_stripe_t *stripes, in
       for (int th : {256, 512, 768, 1024})
         for (int tile : {8 << 10, 16 << 10, 64 << 10, 256 << 10})
           for (int wgs = 1; wgs <= 2; ++wgs)
-            for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE, RS_POLY_TABLES_BITMATRIX})
+            for (int tp : {RS_POLY_TABLES_PACKED, RS_POLY_TABLES_NIBBLE, RS_POLY_TABLES_BITMATRIX,
+                           RS_POLY_TABLES_REGISTERS})
               for (int order = 0; order <= 1; ++order) {
-                // (the bit-sliced kernel has one lane shape; the bytes per
-                // lane only shape the table fallback, and 4 is valid with
-                // every workgroup size)
-                if (tp == RS_POLY_TABLES_BITMATRIX && bpl != 4) continue;
+                // (the bit-sliced and register split-nibble kernels have one
+                // lane shape; the bytes per lane only shape the table
+                // fallback, and 4 is valid with every workgroup size)
+                if ((tp == RS_POLY_TABLES_BITMATRIX || tp == RS_POLY_TABLES_REGISTERS) && bpl != 4)
+                  continue;
                 const rs_poly_launch_t c{bpl, th, tile, wgs, tp, order};
                 if (valid_launch(op, w, c)) cands.push_back(c);
               }

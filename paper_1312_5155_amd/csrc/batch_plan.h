@@ -43,6 +43,7 @@ struct GroupPlan {
   };
   std::map<MatrixKey, uint32_t> matrix_index;
   bool matrix = false;   // update group in the generator-matrix form
+  bool nibble = false;   // update group in the register split-nibble form
   const BitmatrixCode *bm = nullptr;  // encode group of one code, bit-sliced
   std::vector<std::shared_ptr<const DecodePlan>> keep;  // plans alive during the call
   uint64_t tiles = 0;

@@ -17,6 +17,7 @@
 
 #include <utility>
 
+#include "batch_tiles.h"
 #include "rs_internal.h"
 
 namespace rsp {
@@ -298,63 +299,20 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-// The tile loop of the persistent batch kernels (same arena, tile map and
-// claim counter as the table-driven batch kernel; tile_cols a multiple of
-// 2048): the waves of a workgroup take neighbouring 2048-column chunks of
-// each tile they claim, chunk(stripe pointer table, first column, end
-// column, lane) encoding one.
-template <class Chunk>
-__device__ __forceinline__ void batch_tiles(const BatchGroup &g, Chunk &&chunk) {
-  __shared__ uint64_t next_claim;
-  BatchHeader *hdr = reinterpret_cast<BatchHeader *>(g.arena);
-  const const_as<BatchHeader> chdr = (const_as<BatchHeader>)(uintptr_t)hdr;
-  const uint64_t total = chdr->total_tiles;
-  const const_as<StripeDesc> descs =
-      (const_as<StripeDesc>)(uintptr_t)(g.arena + chdr->off_descs);
-  const const_as<uint64_t> ptr_table = (const_as<uint64_t>)(uintptr_t)(g.arena + chdr->off_ptrs);
-  const const_as<uint32_t> tile_stripe = (const_as<uint32_t>)(uintptr_t)g.tile_stripe;
-  unsigned long long *counter = reinterpret_cast<unsigned long long *>(&hdr->counter);
-  const uint32_t tile_cols = chdr->tile_cols;
-  const uint32_t lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6),
-                 waves = blockDim.x >> 6;
-
-  // claim c -> tile: in order (0) or runs of neighbouring tiles per
-  // workgroup (1), as in the table-driven batch kernel
-  const bool runs = chdr->tile_order != 0;
-  const uint64_t P = gridDim.x;
-  const uint64_t run = (total + P - 1) / P;
-  const uint64_t claims = runs ? run * P : total;
-  if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
-  __syncthreads();
-  for (;;) {
-    const uint64_t c =
-        (uint64_t)uniform((uint32_t)(next_claim >> 32)) << 32 | uniform((uint32_t)next_claim);
-    __syncthreads();   // every thread has read next_claim
-    if (c >= claims) break;
-    if (threadIdx.x == 0) next_claim = atomicAdd(counter, 1ull);
-    const uint64_t tile = runs ? (c % P) * run + c / P : c;
-    if (tile < total) {
-      const uint32_t s = tile_stripe[tile];
-      const uint64_t bytes = descs[s].block_bytes;
-      const uint64_t c0 = (tile - descs[s].tile_begin) * tile_cols;
-      const uint64_t c1 = bytes - c0 > tile_cols ? c0 + tile_cols : bytes;
-      const const_as<uint64_t> ptrs = ptr_table + descs[s].ptr_off;
-      for (uint64_t cc = c0 + (uint64_t)wave * kWaveCols; cc < c1; cc += (uint64_t)waves * kWaveCols)
-        chunk(ptrs, cc, c1, lane);
-    }
-    __syncthreads();   // next_claim is about to change
-  }
-}
-
 // Persistent batch kernel of a compiled-in code: every stripe of the group
 // is an RS(K, M) stripe.
 // (at most 2 workgroups of at most 1024 threads per CU: 4 waves per SIMD at
-// 512 threads, so the kernel may use 128 VGPRs and spill nothing)
+// 512 threads, so the kernel may use 128 VGPRs; RS(10,4) spills nothing,
+// the RS(32,8) network keeps a few values in scratch)
 template <int K, int M>
 __global__ void __launch_bounds__(1024)
 __attribute__((amdgpu_waves_per_eu(4))) bitmatrix_batch_kernel(BatchGroup g) {
-  batch_tiles(g, [](const_as<uint64_t> ptrs, uint64_t cc, uint64_t c1, uint32_t lane) {
-    encode_chunk<K, M>(TableBlocks<K, M>{ptrs}, cc, c1, lane);
+  const uint32_t lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6),
+                 waves = blockDim.x >> 6;
+  tiles::run(g, [&](tiles::cptr<StripeDesc>, const_as<uint64_t> ptrs, uint64_t c0, uint64_t c1) {
+    // the waves take neighbouring 2048-column chunks of the tile
+    for (uint64_t cc = c0 + (uint64_t)wave * kWaveCols; cc < c1; cc += (uint64_t)waves * kWaveCols)
+      encode_chunk<K, M>(TableBlocks<K, M>{ptrs}, cc, c1, lane);
   });
 }
 
@@ -464,8 +422,12 @@ __attribute__((amdgpu_waves_per_eu(bitmatrix_waves_per_eu<M>()))) bitmatrix_rt_k
 template <int M>
 __global__ void __launch_bounds__(1024)
 __attribute__((amdgpu_waves_per_eu(4))) bitmatrix_rt_batch_kernel(BitmatrixRtBatch a) {
-  batch_tiles(a.g, [&](const_as<uint64_t> ptrs, uint64_t cc, uint64_t c1, uint32_t lane) {
-    encode_chunk_rt<M>(TableBlocksRt{ptrs, a.k, M}, a.k, a.rows, cc, c1, lane);
+  const uint32_t lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6),
+                 waves = blockDim.x >> 6;
+  tiles::run(a.g, [&](tiles::cptr<StripeDesc>, const_as<uint64_t> ptrs, uint64_t c0,
+                      uint64_t c1) {
+    for (uint64_t cc = c0 + (uint64_t)wave * kWaveCols; cc < c1; cc += (uint64_t)waves * kWaveCols)
+      encode_chunk_rt<M>(TableBlocksRt{ptrs, a.k, M}, a.k, a.rows, cc, c1, lane);
   });
 }
 

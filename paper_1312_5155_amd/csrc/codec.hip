@@ -1193,6 +1193,7 @@ int launch_batch(Mode mode, int sb, const BatchGroup &g, uint64_t max_tiles,
   int err = (int)hipGetLastError();
   if (err) return err;
   if (cfg.bm) return launch_bitmatrix_batch(*cfg.bm, g, cfg.grid, cfg.threads, st);
+  if (cfg.nibble_update) return launch_nibble_batch(g, cfg.grid, cfg.threads, st);
   const int w = cfg.dwords_per_lane;
   BatchFn fn;
   // (the matrix-form update has no LFSR tables: the placement does not apply)

@@ -17,6 +17,7 @@
 // take 8 * C * m VGPRs, so the kernel is built for C <= 2 and C * m <= 8.
 #include <hip/hip_runtime.h>
 
+#include "batch_tiles.h"
 #include "rs_internal.h"
 
 namespace rsp {
@@ -68,31 +69,38 @@ __device__ __forceinline__ uint32_t add_product(uint32_t acc, const uint32_t (&t
   return __builtin_amdgcn_bitop3_b32(acc, lo, hi, 0x96);   // acc ^ lo ^ hi
 }
 
-// One table entry by its byte index, for the byte-wise tail (read from the
-// kernel arguments: a dynamic index into the register copy would put it in
-// scratch memory).
-__device__ __forceinline__ uint32_t entry(const uint32_t *t, int half, uint32_t n) {
+// One table entry by its byte index, for the byte-wise tail (read from
+// memory, the kernel arguments or the batch arena: a dynamic index into the
+// register copy would put it in scratch memory).
+template <class P>
+__device__ __forceinline__ uint32_t entry(P t, int half, uint32_t n) {
   return (t[4 * half + (n >> 2)] >> (8 * (n & 3))) & 0xFFu;
 }
 
-template <int C, int MM>
-__global__ void __launch_bounds__(512) nibble_update_kernel(NibbleParams p) {
+// Columns [c0, c1) of one stripe (c0 a multiple of 16): parity[i] ^= the
+// products of the C changed blocks.  The C * MM tables come from `src`
+// (entry q at src + 8 q, q = t * MM + i) into registers; thread `me` of
+// `count` takes the 16-byte chunks me, me + count, ...; the thread with
+// `tail` set does the last (c1 - c0) mod 16 bytes byte by byte.
+template <int C, int MM, class P>
+__device__ __forceinline__ void nibble_columns(const uint8_t *const (&delta)[C],
+                                               uint8_t *const (&parity)[MM], P src,
+                                               uint64_t c0, uint64_t c1, uint64_t me,
+                                               uint64_t count, bool tail) {
   uint32_t tab[C * MM][8];
 #pragma unroll
   for (int q = 0; q < C * MM; ++q)
 #pragma unroll
-    for (int d = 0; d < 8; ++d) tab[q][d] = p.tab[q][d];
-  const uint64_t B = p.block_bytes;
-  const uint64_t chunks = B / 16;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t ch = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < chunks; ch += stride) {
-    const uint64_t col = ch * 16;
+    for (int d = 0; d < 8; ++d) tab[q][d] = src[8 * q + d];
+  const uint64_t chunks = (c1 - c0) / 16;
+  for (uint64_t ch = me; ch < chunks; ch += count) {
+    const uint64_t col = c0 + ch * 16;
     u32x4 acc[MM];
 #pragma unroll
-    for (int i = 0; i < MM; ++i) acc[i] = load16(p.parity[i] + col);
+    for (int i = 0; i < MM; ++i) acc[i] = load16(parity[i] + col);
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      const u32x4 x = load16(p.delta[t] + col);
+      const u32x4 x = load16(delta[t] + col);
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const Nibbles n = nibbles(x[w]);
@@ -101,23 +109,78 @@ __global__ void __launch_bounds__(512) nibble_update_kernel(NibbleParams p) {
       }
     }
 #pragma unroll
-    for (int i = 0; i < MM; ++i) store16(p.parity[i] + col, acc[i]);
+    for (int i = 0; i < MM; ++i) store16(parity[i] + col, acc[i]);
   }
-  // the last B mod 16 bytes, one thread, byte by byte
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (uint64_t col = chunks * 16; col < B; ++col) {
+  if (tail) {
+    for (uint64_t col = c0 + chunks * 16; col < c1; ++col) {
 #pragma unroll
       for (int i = 0; i < MM; ++i) {
-        uint32_t v = p.parity[i][col];
+        uint32_t v = parity[i][col];
 #pragma unroll
         for (int t = 0; t < C; ++t) {
-          const uint32_t x = p.delta[t][col];
-          v ^= entry(p.tab[t * MM + i], 0, x & 15) ^ entry(p.tab[t * MM + i], 1, x >> 4);
+          const uint32_t x = delta[t][col];
+          v ^= entry(src + 8 * (t * MM + i), 0, x & 15) ^ entry(src + 8 * (t * MM + i), 1, x >> 4);
         }
-        p.parity[i][col] = (uint8_t)v;
+        parity[i][col] = (uint8_t)v;
       }
     }
   }
+}
+
+// One stripe per launch: grid-stride over its 16-byte chunks.
+template <int C, int MM>
+__global__ void __launch_bounds__(512) nibble_update_kernel(NibbleParams p) {
+  const uint8_t *delta[C];
+  uint8_t *parity[MM];
+#pragma unroll
+  for (int t = 0; t < C; ++t) delta[t] = p.delta[t];
+#pragma unroll
+  for (int i = 0; i < MM; ++i) parity[i] = p.parity[i];
+  nibble_columns<C, MM>(delta, parity, &p.tab[0][0], 0, p.block_bytes,
+                        (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                        (uint64_t)gridDim.x * blockDim.x, blockIdx.x == 0 && threadIdx.x == 0);
+}
+
+// Batched updates: persistent workgroups claim tiles of all the stripes of
+// a group.  A stripe's descriptor holds its changed-block count c (field k)
+// and m; its pointer table starts with the c changed delta blocks, then the
+// m parity blocks (read and written in place); its tables are the apply
+// set apply_set of the arena (c * m x 8 dwords).
+template <int C, int MM>
+__device__ __forceinline__ void nibble_tile(tiles::cptr<uint64_t> ptrs, tiles::cptr<uint32_t> tab,
+                                            uint64_t c0, uint64_t c1) {
+  const uint8_t *delta[C];
+  uint8_t *parity[MM];
+#pragma unroll
+  for (int t = 0; t < C; ++t) delta[t] = reinterpret_cast<const uint8_t *>(ptrs[t]);
+#pragma unroll
+  for (int i = 0; i < MM; ++i) parity[i] = reinterpret_cast<uint8_t *>(ptrs[C + i]);
+  nibble_columns<C, MM>(delta, parity, tab, c0, c1, threadIdx.x, blockDim.x, threadIdx.x == 0);
+}
+
+__global__ void __launch_bounds__(1024) nibble_batch_kernel(BatchGroup g) {
+  const BatchHeader *hdr = reinterpret_cast<const BatchHeader *>(g.arena);
+  const tiles::cptr<uint32_t> sets =
+      (tiles::cptr<uint32_t>)(uintptr_t)(g.arena + ((tiles::cptr<BatchHeader>)(uintptr_t)hdr)->off_apply);
+  tiles::run(g, [&](tiles::cptr<StripeDesc> d, tiles::cptr<uint64_t> ptrs, uint64_t c0,
+                    uint64_t c1) {
+    const tiles::cptr<uint32_t> tab = sets + (uint64_t)d->apply_set * (kMaxM * 16);
+    switch (d->k * 16 + d->m) {   // (c, m), uniform
+      case 0x11: nibble_tile<1, 1>(ptrs, tab, c0, c1); break;
+      case 0x12: nibble_tile<1, 2>(ptrs, tab, c0, c1); break;
+      case 0x13: nibble_tile<1, 3>(ptrs, tab, c0, c1); break;
+      case 0x14: nibble_tile<1, 4>(ptrs, tab, c0, c1); break;
+      case 0x15: nibble_tile<1, 5>(ptrs, tab, c0, c1); break;
+      case 0x16: nibble_tile<1, 6>(ptrs, tab, c0, c1); break;
+      case 0x17: nibble_tile<1, 7>(ptrs, tab, c0, c1); break;
+      case 0x18: nibble_tile<1, 8>(ptrs, tab, c0, c1); break;
+      case 0x21: nibble_tile<2, 1>(ptrs, tab, c0, c1); break;
+      case 0x22: nibble_tile<2, 2>(ptrs, tab, c0, c1); break;
+      case 0x23: nibble_tile<2, 3>(ptrs, tab, c0, c1); break;
+      case 0x24: nibble_tile<2, 4>(ptrs, tab, c0, c1); break;
+      default: break;   // not planned for this kernel
+    }
+  });
 }
 
 using NibbleFn = void (*)(NibbleParams);
@@ -147,6 +210,13 @@ NibbleFn pick_nibble(int m) {
 
 bool nibble_supported(int c, int m) {
   return c >= 1 && c <= kNibbleMaxBlocks && m >= 1 && c * m <= kNibbleMaxProducts;
+}
+
+int launch_nibble_batch(const BatchGroup &g, int grid, int threads, void *stream) {
+  if (threads < 64 || threads > 1024 || threads % 64 || grid < 1) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(nibble_batch_kernel, dim3(grid), dim3(threads), 0,
+                     reinterpret_cast<hipStream_t>(stream), g);
+  return (int)hipGetLastError();
 }
 
 int launch_nibble_update(const NibbleParams &p, int grid, void *stream) {

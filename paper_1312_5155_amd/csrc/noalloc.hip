@@ -114,6 +114,7 @@ extern "C" int rs_poly_batch_noalloc(int op, const rs_poly_stripe_t *stripes, in
     lc.grid = ncu * launch[w].wgs_per_cu;
     lc.nibble = launch[w].table_placement == RS_POLY_TABLES_NIBBLE;
     lc.bm = gp.bm;
+    lc.nibble_update = gp.nibble;
     const Mode mode = op == RS_POLY_OP_DECODE   ? kDecode
                       : op == RS_POLY_OP_UPDATE ? (gp.matrix ? kUpdateMatrix : kUpdate)
                                                 : kEncode;

@@ -81,6 +81,7 @@ struct LaunchCfg {
   bool bytewise;         // byte loads/stores (for misaligned blocks)
   bool nibble;           // batch kernels: split-nibble LFSR tables
   const BitmatrixCode *bm = nullptr;   // batch encode: bit-sliced, of this code
+  bool nibble_update = false;          // batch update: register split-nibble kernel
 };
 
 // Launches the codec kernel for one stripe.  Returns a hipError_t as int.
@@ -196,6 +197,15 @@ struct NibbleParams {
 };
 bool nibble_supported(int c, int m);
 int launch_nibble_update(const NibbleParams &p, int grid, void *stream);
+// The persistent batch kernel of the same update (after the pull and
+// prepare kernels): per stripe, descriptor k = c changed blocks, pointer
+// table = the c changed delta blocks then the m parity blocks, tables =
+// apply set apply_set laid out as NibbleParams::tab.
+int launch_nibble_batch(const BatchGroup &g, int grid, int threads, void *stream);
+// Fills the c * m tables of the changed blocks which[0..c) of a code
+// (layout of NibbleParams::tab) into out[c * m][8].
+class Code;
+void nibble_tables(const Code &code, const int *which, int c, uint32_t (*out)[8]);
 
 // Resident workgroups per CU the kernel is sized for (LDS bound).
 int codec_wgs_per_cu(Mode mode);

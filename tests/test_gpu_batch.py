@@ -224,7 +224,9 @@ def test_set_launch_validation():
     bt = B.Batch()
     bad = [dict(bytes_per_lane=3, threads=256, tile_bytes=4096, wgs_per_cu=1),
            dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
-                table_placement=3),
+                table_placement=3),     # register split-nibble: updates only
+           dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
+                table_placement=4),
            dict(bytes_per_lane=4, threads=256, tile_bytes=4096, wgs_per_cu=1,
                 tile_order=2),
            dict(bytes_per_lane=16, threads=300, tile_bytes=4096, wgs_per_cu=1),
@@ -244,6 +246,15 @@ def test_set_launch_validation():
         with pytest.raises(B.RsPolyError):
             bt.set_launch(op, 0, dict(bytes_per_lane=16, threads=512, tile_bytes=4096,
                                       wgs_per_cu=2, table_placement=B.RS_POLY_TABLES_BITMATRIX))
+    # the register split-nibble placement is an update kernel only
+    for w in (0, 1):
+        bt.set_launch(B.RS_POLY_OP_UPDATE, w, dict(bytes_per_lane=4, threads=1024,
+                                                  tile_bytes=16384, wgs_per_cu=2,
+                                                  table_placement=B.RS_POLY_TABLES_REGISTERS))
+    with pytest.raises(B.RsPolyError):
+        bt.set_launch(B.RS_POLY_OP_DECODE, 0, dict(bytes_per_lane=4, threads=512,
+                                                  tile_bytes=4096, wgs_per_cu=2,
+                                                  table_placement=B.RS_POLY_TABLES_REGISTERS))
     # narrow codes at 16 bytes per lane take at most 512 threads; wide codes
     # (m > 4) run every width with up to 1024, 768 included
     with pytest.raises(B.RsPolyError):

@@ -203,8 +203,11 @@ def test_batch_update_mixed_matches_oracle():
         c.check()
 
 
-@pytest.mark.parametrize("placement", [B.RS_POLY_TABLES_PACKED, B.RS_POLY_TABLES_NIBBLE])
+@pytest.mark.parametrize("placement", [B.RS_POLY_TABLES_PACKED, B.RS_POLY_TABLES_NIBBLE,
+                                       B.RS_POLY_TABLES_REGISTERS])
 def test_batch_update_table_placements(placement):
+    # (with REGISTERS most of these stripes change more than 2 blocks, so the
+    # call falls back to the table forms)
     say(f"batch update placement={placement}")
     cases = batch_cases(65, 16, ((10, 4), (32, 8), (6, 3)), 1, 200000)
     bt = B.Batch()
@@ -215,6 +218,59 @@ def test_batch_update_table_placements(placement):
     torch.cuda.synchronize()
     for c in cases:
         c.check()
+
+
+def set_update_placement(bt, placement, threads=None, tile=None):
+    for wide in (0, 1):
+        cfg = bt.get_launch(B.RS_POLY_OP_UPDATE, wide).as_dict()
+        cfg["table_placement"] = placement
+        if threads:
+            cfg.update(bytes_per_lane=4, threads=threads)
+        if tile:
+            cfg["tile_bytes"] = tile
+        bt.set_launch(B.RS_POLY_OP_UPDATE, wide, cfg)
+
+
+@pytest.mark.parametrize("threads,tile,order", [(None, None, 0), (1024, 65536, 1),
+                                                (256, 4096, 0), (512, 16384, 1)])
+def test_batch_update_register_nibble_form(threads, tile, order):
+    # every stripe changes at most 2 blocks (1 for the wide codes, so that
+    # changed * m <= 8): both widths take the register split-nibble kernel;
+    # uneven sizes (ragged tails, blocks under 16 bytes), stripes with no
+    # changed block, m from 1 to 8
+    say(f"batch update, register split-nibble form, threads={threads} tile={tile}")
+    narrow = batch_cases(67, 30, ((6, 3), (10, 4), (12, 4), (3, 1), (5, 2)), 1, 300000,
+                         max_changed=2)
+    wide = batch_cases(68, 12, ((32, 8), (5, 6), (20, 5), (4, 7)), 1, 300000, max_changed=1)
+    cases = narrow + wide
+    bt = B.Batch()
+    set_update_placement(bt, B.RS_POLY_TABLES_REGISTERS, threads, tile)
+    for w in (0, 1):
+        cfg = bt.get_launch(B.RS_POLY_OP_UPDATE, w).as_dict()
+        bt.set_launch(B.RS_POLY_OP_UPDATE, w, dict(cfg, tile_order=order))
+    bt.update(entries(cases))
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check()
+    # and again: the same deltas restore the starting parity
+    bt.update(entries(cases))
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check(want=c.parity0)
+
+
+def test_batch_update_register_form_equals_matrix_form():
+    say("batch update: register split-nibble form vs matrix form")
+    cases = batch_cases(69, 16, ((10, 4), (6, 3), (32, 8)), 4096, 1 << 20, max_changed=1)
+    twins = batch_cases(69, 16, ((10, 4), (6, 3), (32, 8)), 4096, 1 << 20, max_changed=1)
+    bt = B.Batch()
+    set_update_placement(bt, B.RS_POLY_TABLES_REGISTERS)
+    bt.update(entries(cases))
+    B.Batch().update(entries(twins))
+    torch.cuda.synchronize()
+    for a, b in zip(cases, twins):
+        assert np.array_equal(a.parity()[0], b.parity()[0])
+        a.check()
 
 
 def test_batch_update_matrix_form_matches_oracle():
@@ -306,10 +362,12 @@ def test_batch_update_rejects_bad_input():
         c.check(want=c.parity0)      # nothing ran
 
 
-def test_full_size_rs104_256x1MiB_batch_update():
-    # One changed block per stripe of the 256 x 10 x 1 MiB workload; the
-    # oracle checks a column window of sampled stripes.
-    say("full size batch update RS(10,4) 256 x 1 MiB")
+@pytest.mark.parametrize("placement", [B.RS_POLY_TABLES_PACKED, B.RS_POLY_TABLES_REGISTERS])
+def test_full_size_rs104_256x1MiB_batch_update(placement):
+    # One changed block per stripe of the 256 x 10 x 1 MiB workload (matrix
+    # form, or register split-nibble form); the oracle checks a column
+    # window of sampled stripes.
+    say(f"full size batch update RS(10,4) 256 x 1 MiB placement={placement}")
     k, m, nbytes, S = 10, 4, 1 << 20, 256
     gen = torch.Generator(device="cuda")
     gen.manual_seed(workloads.data_seed(1) + 77)
@@ -327,6 +385,7 @@ def test_full_size_rs104_256x1MiB_batch_update():
         ptrs = [None] * k + [par[s, i].data_ptr() for i in range(m)]
         ptrs[int(changed[s])] = delta[s].data_ptr()
         ents.append((c, ptrs, nbytes))
+    set_update_placement(bt, placement)
     bt.update(ents)
     torch.cuda.synchronize()
     F = field()
