@@ -284,7 +284,8 @@ def stream_roof(view, k, n_out, stream, launches=8):
     best = 0.0
     for tile in (65536, 262144):
         for order in (0, 1):
-            args = (view.data_ptr(), n * nb, nb, S, k, n_out, nb, tile, order)
+            args = (view.data_ptr(), view.stride(0), view.stride(1), S, k, n_out, nb, tile,
+                    order)
             for _ in range(2):
                 B.rs_poly_stream_probe(*args, stream=stream)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -319,6 +320,25 @@ def plain_path(codes, stripes, erasures, stream, steps, user):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     return {"ms_per_step": round(ms, 3), "value": round(2 * user / (ms / 1e3) / 1e9, 1),
             "launches_per_step": 2 * len(stripes)}
+
+
+def probe_mixes(dev, stream):
+    """The streaming probe over 64 stripes of 40 blocks of 16 MiB for a range
+    of read:write mixes (n_in inputs, n_out outputs per stripe; the best of
+    its tile sizes and orders): how this part's HBM rate depends on the mix."""
+    import torch
+    S, n, nb = 64, 40, 16 << 20
+    buf = torch.zeros((S, n, nb), dtype=torch.uint8, device=dev)
+    out = []
+    for n_in, n_out in ((39, 1), (38, 2), (36, 4), (32, 8), (24, 8), (16, 8), (8, 8),
+                        (4, 4), (2, 8), (1, 8)):
+        view = buf[:, :n_in + n_out]
+        gbs = stream_roof(view, n_in, n_out, stream)
+        out.append({"n_in": n_in, "n_out": n_out, "gbs": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    del buf
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batched(name, args, dev, stream, src_hash, roofline=False):
@@ -800,6 +820,8 @@ def main():
     ap.add_argument("--traffic-workload", default=HEADLINE, choices=WORKLOADS)
     ap.add_argument("--leg", choices=("plain_encoders", "plain_update_forms"),
                     help="only this one-stripe leg (for profiling its kernels)")
+    ap.add_argument("--probe-mixes", action="store_true",
+                    help="only the streaming probe over a range of read:write mixes")
     args = ap.parse_args()
     loads = [0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.2]
 
@@ -812,6 +834,12 @@ def main():
     if args.serving_sweep:
         res = serving(loads, max(1, args.serving_requests))
         print(json.dumps({"workload": "serving_rs104", **res}), flush=True)
+        return
+    if args.probe_mixes:
+        import torch
+        res = probe_mixes(torch.device("cuda:0"), torch.cuda.current_stream())
+        print(json.dumps({"probe_mixes": res, "stripes": 64, "blocks": 40,
+                          "block_bytes": 16 << 20}), flush=True)
         return
     if args.leg:
         import torch
