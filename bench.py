@@ -894,9 +894,10 @@ def main():
     torch.cuda.empty_cache()
 
     if args.extras:
-        # serving next: in one full run, serving measured after all the
-        # other legs reached about 40% of its capacity measured on its own,
-        # or after any one of those legs (cause not isolated)
+        # serving next, before the other workloads: one full run of an
+        # earlier build measured serving after all the other legs at about
+        # 40% of its capacity on its own (cause not isolated; not seen with
+        # the current build)
         if args.serving_requests > 0:
             extras["serving_rs104"] = serving(loads, args.serving_requests)
         for name in WORKLOADS:
