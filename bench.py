@@ -282,7 +282,7 @@ def stream_roof(view, k, n_out, stream, launches=8):
     from paper_1312_5155_amd import binding as B
     S, n, nb = view.shape
     best = 0.0
-    for tile in (65536, 262144):
+    for tile in (8192, 16384, 65536, 262144):    # the batch kernels' tile sizes
         for order in (0, 1):
             args = (view.data_ptr(), view.stride(0), view.stride(1), S, k, n_out, nb, tile,
                     order)
