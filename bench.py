@@ -330,8 +330,8 @@ def probe_mixes(dev, stream):
     S, n, nb = 64, 40, 16 << 20
     buf = torch.zeros((S, n, nb), dtype=torch.uint8, device=dev)
     out = []
-    for n_in, n_out in ((39, 1), (38, 2), (36, 4), (32, 8), (24, 8), (16, 8), (8, 8),
-                        (4, 4), (2, 8), (1, 8)):
+    for n_in, n_out in ((40, 0), (39, 1), (38, 2), (36, 4), (32, 8), (24, 8), (16, 8),
+                        (8, 8), (4, 4), (2, 8), (1, 8), (0, 8)):
         view = buf[:, :n_in + n_out]
         gbs = stream_roof(view, n_in, n_out, stream)
         out.append({"n_in": n_in, "n_out": n_out, "gbs": round(gbs, 1),

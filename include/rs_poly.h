@@ -231,7 +231,9 @@ int rs_poly_decode_plan(rs_poly_t *h, const int *erasures, int n_erasures,
  *   strides     multiples of 16; blocks and stripes must not overlap:
  *               block_bytes <= block_stride, (n_in + n_out) * block_stride
  *               <= stripe_stride
- *   n_in        1..RS_POLY_MAX_N;  n_out 1..RS_POLY_MAX_M
+ *   n_in        0..RS_POLY_MAX_N;  n_out 0..RS_POLY_MAX_M, not both 0
+ *               (n_out = 0 only reads, n_in = 0 only writes zeros: the
+ *               rates of pure reads and pure writes)
  *   block_bytes multiple of 16, at most 2^31
  *   tile_bytes  columns per tile: a multiple of 16, >= 4096
  *   tile_order  0 or 1

@@ -479,7 +479,8 @@ int rs_poly_stream_probe(uint8_t *base, size_t stripe_stride, size_t block_strid
                         int n_in, int n_out, size_t block_bytes, int tile_bytes, int tile_order,
                         void *stream) {
   if (!base) return RS_ENULL;
-  if (stripes < 0 || n_in < 1 || n_in > RS_POLY_MAX_N || n_out < 1 || n_out > RS_POLY_MAX_M)
+  if (stripes < 0 || n_in < 0 || n_in > RS_POLY_MAX_N || n_out < 0 || n_out > RS_POLY_MAX_M ||
+      n_in + n_out == 0)
     return RS_EINVAL;
   if (pointer_alignment(base) < 16 || stripe_stride % 16 || block_stride % 16 ||
       block_bytes % 16 || block_bytes > kMaxPieceBytes || block_bytes > block_stride ||

@@ -223,8 +223,9 @@ def test_stream_probe_validates_before_any_device_call():
     assert call(st=0) == B.RS_OK                             # nothing to stream
     assert call(bb=0) == B.RS_OK
     assert call(base=ctypes.c_void_p(0x100008)) == B.RS_EINVAL   # 8-byte aligned
-    assert call(ni=0) == B.RS_EINVAL
-    assert call(no=0) == B.RS_EINVAL
+    assert call(ni=0, no=0) == B.RS_EINVAL                    # nothing read or written
+    assert call(ni=-1) == B.RS_EINVAL
+    assert call(no=-1) == B.RS_EINVAL
     assert call(no=9) == B.RS_EINVAL
     assert call(st=-1) == B.RS_EINVAL
     assert call(bb=MiB + 16) == B.RS_EINVAL                   # block over its stride

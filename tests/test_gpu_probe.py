@@ -23,6 +23,8 @@ def say(*a):
     (1, 1, 1, 16, 4096),
     (4, 9, 2, 1 << 20, 65536),
     (5, 3, 3, 1000 * 16, 4096),          # not a multiple of a wave's 2 KiB
+    (2, 7, 0, 65536 + 32, 8192),         # reads only
+    (3, 0, 5, 3 * 4096 + 48, 4096),      # writes only (zeros)
 ])
 @pytest.mark.parametrize("order", [0, 1])
 def test_stream_probe_writes_the_xor_of_its_inputs(S, n_in, n_out, nb, tile, order):
