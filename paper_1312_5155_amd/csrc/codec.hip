@@ -69,12 +69,15 @@ namespace rsp {
 namespace {
 
 // A kernel variant (the MODE template argument below): the operation in the
-// low two bits, the LFSR table placement in the next one.
+// low two bits, the LFSR table placement in the next one, then the wide
+// matrix form, then the interleaved M = 8 state layout.
 constexpr int kNibbleBit = 4;
 constexpr int kWideMatrixBit = 8;   // kUpdateMatrixWide = kUpdateMatrix | this
+constexpr int kIlvBit = 16;
 constexpr int op_of(int v) { return v & 3; }
 constexpr bool nibble_of(int v) { return (v & kNibbleBit) != 0; }
 constexpr bool wide_matrix_of(int v) { return (v & kWideMatrixBit) != 0; }
+constexpr bool ilv_of(int v) { return (v & kIlvBit) != 0; }
 static_assert(kUpdateMatrixWide == (kUpdateMatrix | kWideMatrixBit), "mode encoding");
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
@@ -182,8 +185,19 @@ struct Layout {
   static constexpr uint32_t kApplyBase = kTwoRegions ? 65536 : 128;
   // Wide matrix form: 32 tables in two 64 KiB regions of 16 tables each.
   static constexpr bool kWideMatrix = wide_matrix_of(MODE);
+  // Interleaved M = 8 layout (see below): LFSR copies of even rotation
+  // index in region 0, odd in region 1 (64 KiB each, 4 copies x 8
+  // replicas per row); decode adds split-nibble apply tables in region 2
+  // (64 rows: low-nibble and high-nibble tables of the even remainder
+  // bytes, then of the odd ones, 4 tables x 8 replicas per row).
+  static constexpr bool kIlv = M == 8 && ilv_of(MODE) && !kNibble && op_of(MODE) != kUpdateMatrix;
+  static constexpr uint32_t kIlvReps = 8;
+  static constexpr uint32_t kIlvTableBytes = kIlvReps * 8;
+  static constexpr uint32_t kIlvApplyBase = 131072;
+  static constexpr uint32_t kIlvApplyRows = 64;
   static constexpr uint32_t kLdsBytes =
-      kTwoRegions || kWideMatrix ? 131072
+      kIlv ? (op_of(MODE) == kDecode ? kIlvApplyBase + kIlvApplyRows * kRowBytes : 131072)
+      : kTwoRegions || kWideMatrix ? 131072
       : kNibble && op_of(MODE) != kDecode ? 32 * kRowBytes : 65536;
   // Matrix update: one table per changed block, a group of M tables per
   // item (the item's M blocks), kMatReps replicas; 2 groups per row for
@@ -213,6 +227,21 @@ struct Layout {
 // so a step selects it with a v_perm over both dwords and ORs in the lane
 // offset; rotations into and out of the phase are v_perm byte shuffles of
 // the dword pair.
+//
+// Interleaved M = 8 (the wide kernels at 16 bytes per lane): the state
+// keeps the even bytes of the 8-byte value in its first dword and the odd
+// ones in its second, and only even phases g = 2h (h = 0..3) are used.  At
+// step q every lane's feedback byte (q + g) mod 8 then sits in dword q & 1,
+// at position (q/2 + h) mod 4, so one v_perm of (that dword, an offset
+// register) forms the whole address: byte 1 the feedback byte, byte 0 the
+// lane's slot in the row, byte 2 the region (copies of odd rotation index
+// are 64 KiB up).  The 32 lanes of a pass use 4 copies (one parity) x 8
+// replicas, all distinct banks.  Rotation by g moves bytes only within a
+// dword, so items enter and parity leaves through the rotating transpose
+// selectors, as for M = 4, and no state is ever rotated back.  The decode
+// apply reads remainder byte (b - g) mod 8 at step b, which sits at the
+// same position b/2 in every lane (a uniform selector), from split-nibble
+// tables (two lookups per byte) that fit beside the 128 KiB of LFSR copies.
 template <int M, int MODE>
 struct Lanes {
   uint32_t lsel[M], loff[M];   // LFSR step q: v_perm selector, byte offset
@@ -220,13 +249,44 @@ struct Lanes {
   uint32_t tin[2], tout[2];    // M = 4: rotating transpose selectors (in, out)
   uint32_t rin[2], rout[2];    // M = 8: v_perm selectors (low, high dword)
   uint32_t asel[M], aoff[M];   // decode apply, slot b
+  uint32_t isel[4];            // interleaved: selector of steps 2j, 2j + 1
+  uint32_t ioff[4];            // interleaved: slot offsets, region 0 (x2), region 1 (x2)
+  uint32_t iapp[2];            // interleaved decode: apply slot offsets, region 2
 };
 
 template <int M, int MODE>
 __device__ __forceinline__ Lanes<M, MODE> make_lanes() {
   using L = Layout<M, MODE>;
-  Lanes<M, MODE> t;
+  Lanes<M, MODE> t{};
   const uint32_t lane = threadIdx.x & 63;
+  if constexpr (L::kIlv) {
+    const uint32_t h = (lane >> 3) & 3, rep = lane & 7;
+    uint32_t off[4], aof[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      // steps 2j, 2j + 1 read copies 2((j + h) mod 4) and that plus one;
+      // apply step 2j (+1) reads table 2((j - h) mod 4) (+1)
+      off[j] = ((j + h) & 3) * L::kIlvTableBytes + rep * 8;
+      aof[j] = ((j - h) & 3) * L::kIlvTableBytes + rep * 8;
+      // byte 0 <- offset byte j & 1, byte 1 <- state byte (j + h) mod 4,
+      // byte 2 <- offset byte 2 (the region), byte 3 <- 0
+      t.isel[j] = (j & 1) | ((4 + ((j + h) & 3)) << 8) | (2u << 16) | (0x0Cu << 24);
+    }
+#pragma unroll
+    for (uint32_t x = 0; x < 2; ++x) {
+      t.ioff[x] = off[2 * x] | (off[2 * x + 1] << 8);
+      t.ioff[2 + x] = t.ioff[x] | (1u << 16);
+      t.iapp[x] = aof[2 * x] | (aof[2 * x + 1] << 8) | ((L::kIlvApplyBase >> 16) << 16);
+    }
+    t.tin[0] = rotl32(kT2a, 8 * h);
+    t.tin[1] = rotl32(kT2b, 8 * h);
+#pragma unroll
+    for (uint32_t i = 0; i < 2; ++i) {
+      t.tout[0] |= (((i + h) & 3) | (((4 + ((i + h) & 3))) << 8)) << (16 * i);
+      t.tout[1] |= (((i + 2 + h) & 3) | (((4 + ((i + 2 + h) & 3))) << 8)) << (16 * i);
+    }
+    return t;
+  }
   const uint32_t g = (lane / L::kLfsrReps) % L::kPhases;
   const uint32_t rep = lane & (L::kLfsrReps - 1);
 #pragma unroll
@@ -312,11 +372,27 @@ __device__ __forceinline__ uint2 entry_of(uint32_t f, const uint32_t *basis, int
   }
 }
 
+// An 8-byte entry in the interleaved layout: even bytes in the first dword,
+// odd bytes in the second.
+__device__ __forceinline__ uint2 interleave(uint2 v) {
+  return make_uint2(perm(v.y, v.x, 0x06040200u), perm(v.y, v.x, 0x07050301u));
+}
+
 // Expands the LFSR tables: copy v (0..M-1) of entry f is rotl(T'[f], 8(v+1));
-// split-nibble: row r < 16 holds entry r, row 16 + r entry r << 4.
+// split-nibble: row r < 16 holds entry r, row 16 + r entry r << 4;
+// interleaved: copy v in region v & 1 at table v >> 1 of the row.
 template <int M, int MODE>
 __device__ void build_lfsr_tables(uint8_t *lds, const uint32_t *basis) {
   using L = Layout<M, MODE>;
+  if constexpr (L::kIlv) {
+#pragma unroll
+    for (uint32_t region = 0; region < 2; ++region)
+      fill_tables(lds + 65536 * region, 256, 0, 4, L::kIlvTableBytes,
+                  [&](uint32_t f, uint32_t c) {
+                    return interleave(entry_of<M>(f, basis, (int)(2 * c + region) + 1));
+                  });
+    return;
+  }
   fill_tables(lds, L::kNibble ? 32 : 256, 0, L::kCopies, L::kCopyBytes,
               [&](uint32_t r, uint32_t v) {
                 const uint32_t f = !L::kNibble ? r : r < 16 ? r : (r - 16) << 4;
@@ -325,10 +401,24 @@ __device__ void build_lfsr_tables(uint8_t *lds, const uint32_t *basis) {
 }
 
 // Expands the decode apply tables U'_b, b < m (unused tables are zero).
-template <int M>
+// Interleaved: rows 16G + n of region 2 hold, for G = 0..3, the entries n
+// (G even) or n << 4 (G odd) of the tables of remainder bytes b = 2c + G/2
+// at table c of the row; the entries themselves keep the natural byte
+// order (byte e the product for erased block e).
+template <int M, int MODE>
 __device__ void build_apply_tables(uint8_t *lds, const uint32_t *basis /* [kMaxM][16] */,
                                    int m) {
-  using L = Layout<M, kDecode>;
+  using L = Layout<M, MODE>;
+  if constexpr (L::kIlv) {
+    fill_tables(lds + L::kIlvApplyBase, L::kIlvApplyRows, 0, 4, L::kIlvTableBytes,
+                [&](uint32_t r, uint32_t c) {
+                  const uint32_t grp = r >> 4, n = r & 15;
+                  const uint32_t f = grp & 1 ? n << 4 : n;
+                  const int b = (int)(2 * c + (grp >> 1));
+                  return b < m ? entry_of<M>(f, basis + 16 * b, 0) : make_uint2(0u, 0u);
+                });
+    return;
+  }
   fill_tables(lds, 256, L::kApplyBase, M, L::kTableBytes,
               [&](uint32_t f, uint32_t b) {
                 return (int)b < m ? entry_of<M>(f, basis + 16 * b, 0) : make_uint2(0u, 0u);
@@ -499,6 +589,12 @@ __device__ __forceinline__ void lfsr_step(uint32_t (&s)[M / 4], const uint8_t *l
   } else if constexpr (M == 4) {
     const uint32_t addr = perm(s[0], t.loff[q], t.lsel[q]);
     s[0] ^= *reinterpret_cast<const uint32_t *>(lds + addr);
+  } else if constexpr (Layout<M, MODE>::kIlv) {
+    // feedback byte in dword q & 1; region q & 1 comes with the offsets
+    const uint32_t addr = perm(s[q & 1], t.ioff[2 * (q & 1) + (q >> 2)], t.isel[q >> 1]);
+    const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
+    s[0] ^= v.x;
+    s[1] ^= v.y;
   } else {
     const uint32_t addr = perm(s[1], s[0], t.lsel[q]) | t.loff[q];
     const uint2 v = *reinterpret_cast<const uint2 *>(lds + addr);
@@ -513,6 +609,7 @@ struct PlainSrc {
   const CodecParams &p;
   __device__ const uint8_t *data(int j) const { return p.data[j]; }
   __device__ const uint8_t *par_in(int i) const { return p.par_in[i]; }
+  __device__ const uint8_t *input(int x) const { return x < p.k ? p.data[x] : p.par_in[x - p.k]; }
   __device__ uint8_t *out(int o) const { return p.out[o]; }
   __device__ uint32_t B() const { return p.block_bytes; }
   __device__ int k() const { return p.k; }
@@ -558,6 +655,9 @@ struct TableSrc {
   __device__ const uint8_t *par_in(int i) const {
     return reinterpret_cast<const uint8_t *>(ptrs[kk + i]);
   }
+  __device__ const uint8_t *input(int x) const {   // data x < k, then parity
+    return reinterpret_cast<const uint8_t *>(ptrs[x]);
+  }
   __device__ uint8_t *out(int o) const { return reinterpret_cast<uint8_t *>(ptrs[kk + mm + o]); }
   __device__ uint32_t B() const { return bytes; }
   __device__ int k() const { return kk; }
@@ -583,16 +683,13 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
   const uint32_t B = src.B();
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    const uint8_t *ptr;
-    if (dummy) {
-      ptr = nullptr;
-    } else if (op_of(MODE) != kEncode && g == groups) {
-      const int i = src.m() - 1 - q;
-      ptr = i >= 0 ? src.par_in(i) : nullptr;
-    } else {
-      const int j = src.k_pad() - 1 - (g * M + q);
-      ptr = j < src.k() ? src.data(j) : nullptr;
-    }
+    // Input x of the stripe (data block x < k, then the parity read), one
+    // table index for both kinds of item: a single uniform load per slot
+    // (separate data and parity branches hold more scalar registers live).
+    const bool par = op_of(MODE) != kEncode && g == groups;
+    const int x = par ? src.k() + src.m() - 1 - q : src.k_pad() - 1 - (g * M + q);
+    const bool ok = !dummy && (par ? q < src.m() : x < src.k());
+    const uint8_t *ptr = ok ? src.input(x) : nullptr;
     if constexpr (BYTEWISE) {
       if (ptr) {
         load_cols<W, true>(ptr, col, B, a[q]);
@@ -651,14 +748,23 @@ __device__ __forceinline__ void absorb_xor_item(uint32_t (&s)[4 * W][M / 4],
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     uint32_t d[NQ][4];
+    if constexpr (Layout<M, MODE>::kIlv) {
+      // even window positions to dword 0, odd to dword 1, both rotated into
+      // the lane's phase by the second round (data and parity items alike)
+      transpose4(a[0][w], a[2][w], a[4][w], a[6][w], d[0][0], d[0][1], d[0][2], d[0][3],
+                 kT1a, kT1b, t.tin[0], t.tin[1]);
+      transpose4(a[1][w], a[3][w], a[5][w], a[7][w], d[NQ - 1][0], d[NQ - 1][1],
+                 d[NQ - 1][2], d[NQ - 1][3], kT1a, kT1b, t.tin[0], t.tin[1]);
+    } else {
 #pragma unroll
-    for (int h = 0; h < NQ; ++h) {
-      if constexpr (M == 4 && !kMatrix)
-        transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
-                   d[h][1], d[h][2], d[h][3], kT1a, kT1b, t.tin[0], t.tin[1]);
-      else
-        transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
-                   d[h][1], d[h][2], d[h][3]);
+      for (int h = 0; h < NQ; ++h) {
+        if constexpr (M == 4 && !kMatrix)
+          transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
+                     d[h][1], d[h][2], d[h][3], kT1a, kT1b, t.tin[0], t.tin[1]);
+        else
+          transpose4(a[4 * h][w], a[4 * h + 1][w], a[4 * h + 2][w], a[4 * h + 3][w], d[h][0],
+                     d[h][1], d[h][2], d[h][3]);
+      }
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
@@ -688,7 +794,7 @@ __device__ __forceinline__ void absorb_xor_item(uint32_t (&s)[4 * W][M / 4],
 #pragma unroll
           for (int h = 0; h < NQ; ++h) d[h][x] = acc[h];
         }
-      } else if constexpr (M == 8) {
+      } else if constexpr (M == 8 && !Layout<M, MODE>::kIlv) {
         if constexpr (lfsr) {
           const uint32_t lo = perm(d[1][x], d[0][x], t.rin[0]);
           const uint32_t hi = perm(d[1][x], d[0][x], t.rin[1]);
@@ -740,7 +846,7 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
 // (M = 4 keeps them rotated; see Lanes).
 template <int M, int W, int MODE>
 __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lanes<M, MODE> &t) {
-  if constexpr (M == 8) {
+  if constexpr (M == 8 && !Layout<M, MODE>::kIlv) {
 #pragma unroll
     for (int c = 0; c < 4 * W; ++c) {
       const uint32_t lo = perm(s[c][1], s[c][0], t.rout[0]);
@@ -774,8 +880,48 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
     // (8 columns x 8 products x 2 dwords).
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      if constexpr (NC > 1) {
+      if constexpr (NC > 1 && !Layout<M, MODE>::kIlv) {
         if ((c & 1) == 0) pin_pair(s[c], s[c + 1]);
+      }
+      if constexpr (Layout<M, MODE>::kIlv) {
+        // Nibbles of the remainder bytes, each with its table group's row
+        // base (+16 high nibbles, +32 odd bytes); step b looks up both
+        // nibbles of byte (b - g) mod 8, at position b/2 of dword b & 1.
+        // The 16 lookups go in two halves, the second issued after the
+        // first is summed (the empty asm), so that a column holds 8
+        // products at a time.
+        uint32_t nib[2][2];
+        nib[0][0] = s[c][0] & 0x0F0F0F0Fu;
+        nib[0][1] = __builtin_amdgcn_bitop3_b32(s[c][0] >> 4, 0x0F0F0F0Fu, 0x10101010u, 0xEA);
+        nib[1][0] = __builtin_amdgcn_bitop3_b32(s[c][1], 0x0F0F0F0Fu, 0x20202020u, 0xEA);
+        nib[1][1] = __builtin_amdgcn_bitop3_b32(s[c][1] >> 4, 0x0F0F0F0Fu, 0x30303030u, 0xEA);
+        uint32_t acc[2] = {0u, 0u};
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          uint32_t v[M][2];
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            const int b = 4 * half + (i >> 1), hl = i & 1;
+            const uint32_t j = b >> 1;
+            const uint32_t sel = (j & 1) | ((4 + j) << 8) | (2u << 16) | (0x0Cu << 24);
+            const uint32_t addr = perm(nib[b & 1][hl], t.iapp[j >> 1], sel);
+            const uint2 x = *reinterpret_cast<const uint2 *>(lds + addr);
+            v[i][0] = x.x;
+            v[i][1] = x.y;
+          }
+#pragma unroll
+          for (int h = 0; h < NQ; ++h) {
+            uint32_t L = xor3(acc[h], v[0][h], v[1][h]);
+            L = xor3(L, v[2][h], v[3][h]);
+            L = xor3(L, v[4][h], v[5][h]);
+            acc[h] = xor3(L, v[6][h], v[7][h]);
+          }
+          asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(nib[0][0]), "+v"(nib[0][1]),
+                       "+v"(nib[1][0]), "+v"(nib[1][1]));
+        }
+        s[c][0] = acc[0];
+        s[c][1] = acc[1];
+        continue;
       }
       uint32_t v[M][NQ];
 #pragma unroll
@@ -821,10 +967,13 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
 #pragma unroll
   for (int h = 0; h < NQ; ++h) {
     uint32_t o[4][W];
+    // encode and update (M = 4 or interleaved): the state is still rotated
+    // by the lane's phase; interleaved: output bb of dword h is byte 2bb + h
+    constexpr bool kRotated = (M == 4 || Layout<M, MODE>::kIlv) && op_of(MODE) != kDecode &&
+                              op_of(MODE) != kUpdateMatrix;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      if constexpr (M == 4 && op_of(MODE) != kDecode &&
-                    op_of(MODE) != kUpdateMatrix)   // state still rotated by g
+      if constexpr (kRotated)
         transpose4(s[4 * w][h], s[4 * w + 1][h], s[4 * w + 2][h], s[4 * w + 3][h], o[0][w],
                    o[1][w], o[2][w], o[3][w], t.tout[0], t.tout[1]);
       else
@@ -833,11 +982,27 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
     }
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-      const int b = 4 * h + bb;
+      const int b = kRotated && M == 8 ? 2 * bb + h : 4 * h + bb;
       const int oi = op_of(MODE) == kDecode ? b : m - 1 - b;
       if (oi >= 0 && oi < n_out && active)
         store_cols<W, BYTEWISE>(src.out(oi), col, src.B(), o[bb]);
     }
+  }
+}
+
+// An empty asm that takes and gives back every column state and may touch
+// memory: the XORs of an item into the states complete before it, and no
+// load is issued above it.  (A scheduling barrier alone leaves earlier
+// passes free to sink the XORs below the next item's loads, which then need
+// registers of their own.)
+template <int W, int NQ>
+__device__ __forceinline__ void fence_states(uint32_t (&s)[4 * W][NQ]) {
+#pragma unroll
+  for (int c = 0; c < 4 * W; c += 2) {
+    if constexpr (NQ == 1)
+      asm volatile("" : "+v"(s[c][0]), "+v"(s[c + 1][0])::"memory");
+    else
+      asm volatile("" : "+v"(s[c][0]), "+v"(s[c][1]), "+v"(s[c + 1][0]), "+v"(s[c + 1][1])::"memory");
   }
 }
 
@@ -904,8 +1069,8 @@ __device__ __forceinline__ void process_columns(const Src &src, uint32_t c0, uin
       }
       const bool more = nr < rounds;
       absorb_xor<M, W, MODE>(s, a, g < groups, g, lds, t);
-      // (keeps the next loads after the XOR, so they reuse the registers)
-      __builtin_amdgcn_sched_barrier(0);
+      // keeps the next loads after the XOR, so they reuse the registers
+      fence_states<W>(s);
       load_item<M, W, MODE, BYTEWISE>(src, col_of(more ? nr : r), more ? ng : g, groups, !more,
                                       a);
       absorb_steps<M, W, MODE>(s, g < groups, g == 0 ? lead : 0, lds, t);
@@ -991,7 +1156,8 @@ codec_kernel(CodecParams p) {
     build_matrix_tables<M>(lds, &p.apply_basis[0][0], p.k, p.k_pad);
   } else {
     build_lfsr_tables<M, MODE>(lds, p.lfsr_basis);
-    if constexpr (op_of(MODE) == kDecode) build_apply_tables<M>(lds, &p.apply_basis[0][0], p.m);
+    if constexpr (op_of(MODE) == kDecode)
+      build_apply_tables<M, MODE>(lds, &p.apply_basis[0][0], p.m);
   }
   __syncthreads();
 
@@ -1108,7 +1274,8 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
         if (new_apply)
           build_matrix_tables<M>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.k, d.k_pad);
       } else {
-        if (new_apply) build_apply_tables<M>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.m);
+        if (new_apply)
+          build_apply_tables<M, MODE>(lds, apply_sets + kMaxM * 16 * d.apply_set, d.m);
       }
       staged_lfsr = d.lfsr_set;
       staged_apply = d.apply_set;
@@ -1127,6 +1294,14 @@ __attribute__((amdgpu_waves_per_eu(M == 4 ? 4 : 2))) batch_kernel(BatchGroup g) 
 using KernelFn = void (*)(CodecParams);
 using BatchFn = void (*)(BatchGroup);
 
+// The wide kernels at 16 bytes per lane take the interleaved M = 8 layout
+// for the LFSR operations with packed tables: they run one workgroup per CU
+// (128 VGPRs at 1024 threads) whatever their LDS, so its 128-144 KiB cost
+// no occupancy.  Narrower kernels keep the 64 KiB layout.
+constexpr int wide_mode(int mode) {
+  return op_of(mode) == kUpdateMatrix || nibble_of(mode) ? mode : mode | kIlvBit;
+}
+
 template <int MODE>
 KernelFn pick(int sb, int w, bool bytewise) {
   if (bytewise) return sb == 4 ? codec_kernel<4, 1, MODE, true> : codec_kernel<8, 1, MODE, true>;
@@ -1135,7 +1310,7 @@ KernelFn pick(int sb, int w, bool bytewise) {
     if (w == 2) return codec_kernel<4, 2, MODE, false>;
     return codec_kernel<4, 1, MODE, false>;
   }
-  if (w == 4) return codec_kernel<8, 4, MODE, false>;
+  if (w == 4) return codec_kernel<8, 4, wide_mode(MODE), false>;
   if (w >= 2) return codec_kernel<8, 2, MODE, false>;
   return codec_kernel<8, 1, MODE, false>;
 }
@@ -1147,7 +1322,7 @@ BatchFn pick_batch(int sb, int w) {
     if (w == 2) return batch_kernel<4, 2, MODE>;
     return batch_kernel<4, 1, MODE>;
   }
-  if (w == 4) return batch_kernel<8, 4, MODE>;
+  if (w == 4) return batch_kernel<8, 4, wide_mode(MODE)>;
   if (w >= 2) return batch_kernel<8, 2, MODE>;
   return batch_kernel<8, 1, MODE>;
 }
