@@ -88,6 +88,10 @@ def batch_variant(op, launch, m=4, matrix_update=False, k=10):
         return f"bitmatrix_batch_kernel<{k}, {m}>"
     else:
         mode = op + (4 if launch["table_placement"] == 1 else 0)
+        # m > 4 at 16 bytes per lane with packed tables: the interleaved
+        # state layout (mode bit 16)
+        if m > 4 and launch["bytes_per_lane"] == 16 and launch["table_placement"] == 0:
+            mode |= 16
     return f"batch_kernel<{4 if m <= 4 else 8}, {launch['bytes_per_lane'] // 4}, {mode}>"
 
 

@@ -683,13 +683,25 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
   const uint32_t B = src.B();
 #pragma unroll
   for (int q = 0; q < M; ++q) {
-    // Input x of the stripe (data block x < k, then the parity read), one
-    // table index for both kinds of item: a single uniform load per slot
-    // (separate data and parity branches hold more scalar registers live).
-    const bool par = op_of(MODE) != kEncode && g == groups;
-    const int x = par ? src.k() + src.m() - 1 - q : src.k_pad() - 1 - (g * M + q);
-    const bool ok = !dummy && (par ? q < src.m() : x < src.k());
-    const uint8_t *ptr = ok ? src.input(x) : nullptr;
+    const uint8_t *ptr;
+    if constexpr (M == 8) {
+      // Input x of the stripe (data block x < k, then the parity read), one
+      // table index for both kinds of item: a single uniform load per slot
+      // (separate data and parity branches hold more scalar registers live,
+      // more than the wide kernels have to spare).
+      const bool par = op_of(MODE) != kEncode && g == groups;
+      const int x = par ? src.k() + src.m() - 1 - q : src.k_pad() - 1 - (g * M + q);
+      const bool ok = !dummy && (par ? q < src.m() : x < src.k());
+      ptr = ok ? src.input(x) : nullptr;
+    } else if (dummy) {
+      ptr = nullptr;
+    } else if (op_of(MODE) != kEncode && g == groups) {
+      const int i = src.m() - 1 - q;
+      ptr = i >= 0 ? src.par_in(i) : nullptr;
+    } else {
+      const int j = src.k_pad() - 1 - (g * M + q);
+      ptr = j < src.k() ? src.data(j) : nullptr;
+    }
     if constexpr (BYTEWISE) {
       if (ptr) {
         load_cols<W, true>(ptr, col, B, a[q]);
