@@ -29,7 +29,9 @@
 // alpha^i are the paper's step-1 values D(alpha^i).  The erased symbols are
 // then C * r for a small per-pattern matrix C = V^-1 W (Vandermonde inverse
 // computed once per pattern on the host: Opt3), applied as m packed product
-// lookups, one per remainder byte (region-level multiply-XOR: Opt4).
+// lookups, one per remainder byte (region-level multiply-XOR: Opt4); the
+// interleaved m > 4 kernels look up the two nibbles of each byte in
+// split-nibble tables instead.
 //
 // Update = the update property of Sec. 3.2: encoding is linear, so new
 // parity = old parity + encode(delta), delta = new data - old data.  It is
@@ -48,11 +50,13 @@
 // every workgroup from 8 basis values passed in the kernel arguments.  Entry
 // e of every table sits at byte e*256 plus the table's offset and the
 // lane's replica offset, so one v_perm_b32 of (state, lane offset) yields
-// the address (M = 4; a v_perm and an OR for M = 8).  Replicas spread the
-// lanes of a wave over banks, and lanes start at different rotation phases,
-// so that one read spreads over all copies.  64 KiB per workgroup (8 KiB for
-// split-nibble encode/update tables; 128 KiB, one workgroup per CU, for the
-// decode of m > 4).
+// the address (M = 4, and M = 8 in the interleaved layout of the 16-byte
+// kernels; a v_perm and an OR in the narrower M = 8 kernels).  Replicas
+// spread the lanes of a wave over banks, and lanes start at different
+// rotation phases, so that one read spreads over all copies.  64 KiB per
+// workgroup (8 KiB for split-nibble encode/update tables; 128 KiB for the
+// narrow decode of m > 4; 128 KiB, 144 KiB for decode, in the interleaved
+// layout, whose kernels run one workgroup per CU anyway).
 //
 // Memory-level parallelism.  The kernels stream every byte once; throughput
 // is set by the bytes in flight per CU and by how local the concurrent
