@@ -99,8 +99,11 @@ rs_poly_launch_t default_launch(int op, int wide) {
     c.threads = 512;
     c.tile_bytes = op == RS_POLY_OP_ENCODE ? 8 << 10 : 16 << 10;
   }
-  // (a wide decode workgroup takes 128 KiB of LDS: one fits per CU)
-  c.wgs_per_cu = wide && op == RS_POLY_OP_DECODE ? 1 : 2;
+  // Two workgroups per CU in the grid.  The wide kernels run one at a time
+  // per CU (128 VGPRs at 1024 threads; 128-144 KiB of LDS), and the grid of
+  // two still decides the tile walk of tile order 1: measured 0.5% faster
+  // for the RS(32,8) decode than a grid of one.
+  c.wgs_per_cu = 2;
   // Updates: the register split-nibble kernel when every stripe of a width
   // changes at most 2 blocks (2-3% faster than the matrix form on the 1 MiB
   // and 16 MiB workloads); any other update call runs the packed forms.

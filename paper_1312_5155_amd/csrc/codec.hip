@@ -713,6 +713,11 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
 #pragma unroll
         for (int w = 0; w < W; ++w) a[q][w] = 0;
       }
+    } else if (M == 4 && ptr == nullptr) {
+      // (the narrow codes skip an absent block's loads: measured 1-2.5%
+      // faster than reading the zero page; the wide ones are not)
+#pragma unroll
+      for (int w = 0; w < W; ++w) a[q][w] = 0;
     } else {
       const bool absent = ptr == nullptr;
       load_cols<W, false>(absent ? src.zero() : ptr, absent ? col & (kZeroPageBytes - 16) : col,
