@@ -227,10 +227,10 @@ struct Layout {
 // through a first transpose round that reads byte b + g: the rotation costs
 // no instruction.
 //
-// M = 8: the state is two dwords, and byte (q + g) mod 8 may sit in either,
-// so a step selects it with a v_perm over both dwords and ORs in the lane
-// offset; rotations into and out of the phase are v_perm byte shuffles of
-// the dword pair.
+// M = 8 in the narrower kernels: the state is two dwords, and byte
+// (q + g) mod 8 may sit in either, so a step selects it with a v_perm over
+// both dwords and ORs in the lane offset; rotations into and out of the
+// phase are v_perm byte shuffles of the dword pair.
 //
 // Interleaved M = 8 (the wide kernels at 16 bytes per lane): the state
 // keeps the even bytes of the 8-byte value in its first dword and the odd
@@ -674,13 +674,15 @@ struct TableSrc {
 // Loads item g of a column chunk: for g < k_pad/M the M data blocks of LFSR
 // group g (window position q holds block k_pad-1-(g*M+q)); for decode and
 // update, item k_pad/M holds the parity read, position b holding p_(m-1-b).  Blocks not
-// read (erased, unread, padding) give zeros.  In the vector form every slot
-// issues its load -- an absent block reads the zero page at an offset kept
-// inside it -- so the number of loads in flight never depends on the path
-// and the compiler can wait for exactly the item it is about to use.  A
-// dummy item (the prefetch slot after a lane's last item) reads only the
-// zero page, which stays in cache: re-reading real blocks there would fetch
-// them from HBM a second time, since block loads do not keep lines in L2.
+// read (erased, unread, padding) give zeros.  In the vector form of the
+// wide (M = 8) kernels every slot issues its load -- an absent block reads
+// the zero page at an offset kept inside it -- so the number of loads in
+// flight never depends on the path and the compiler can wait for exactly
+// the item it is about to use; the narrow kernels skip an absent block's
+// loads (measured faster there, though the compiler then waits for every
+// load in flight).  A dummy item (the prefetch slot after a lane's last
+// item) has only absent slots: re-reading real blocks there would fetch them
+// from HBM a second time, since block loads do not keep lines in L2.
 template <int M, int W, int MODE, bool BYTEWISE, class Src>
 __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, int groups,
                                           bool dummy, uint32_t (&a)[M][W]) {
@@ -714,8 +716,6 @@ __device__ __forceinline__ void load_item(const Src &src, uint32_t col, int g, i
         for (int w = 0; w < W; ++w) a[q][w] = 0;
       }
     } else if (M == 4 && ptr == nullptr) {
-      // (the narrow codes skip an absent block's loads: measured 1-2.5%
-      // faster than reading the zero page; the wide ones are not)
 #pragma unroll
       for (int w = 0; w < W; ++w) a[q][w] = 0;
     } else {
@@ -748,9 +748,10 @@ __device__ __forceinline__ void matrix_lookups(uint32_t d0, uint32_t d1, uint32_
 
 // XORs item g into the column states.  The item is transposed so that each
 // column's M symbols fill its state window.  An LFSR group is rotated into
-// the lane's phase (for M = 4 every item is, since the state stays rotated;
-// for M = 8 only LFSR groups, since the state is brought back before the
-// parity item), then runs its M steps.  The first `skip` steps are left
+// the lane's phase (for M = 4 and the interleaved layout every item is,
+// since the state stays rotated; for the other M = 8 kernels only LFSR
+// groups, since the state is brought back before the parity item), then
+// runs its M steps.  The first `skip` steps are left
 // out: they are the leading window positions of the first group that hold
 // no block (padding or absent blocks above every present one), where the
 // state is still zero, so the feedback is zero and a step changes nothing.
@@ -863,8 +864,9 @@ __device__ __forceinline__ void absorb_item(uint32_t (&s)[4 * W][M / 4], const u
   absorb_steps<M, W, MODE>(s, data_item, skip, lds, t);
 }
 
-// M = 8: brings the column states back from the lane's rotation phase
-// (M = 4 keeps them rotated; see Lanes).
+// M = 8, narrower kernels: brings the column states back from the lane's
+// rotation phase (M = 4 and the interleaved layout keep them rotated; see
+// Lanes).
 template <int M, int W, int MODE>
 __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lanes<M, MODE> &t) {
   if constexpr (M == 8 && !Layout<M, MODE>::kIlv) {
@@ -880,7 +882,9 @@ __device__ __forceinline__ void unrotate(uint32_t (&s)[4 * W][M / 4], const Lane
 
 // After the last item of a chunk: byte b of the state is remainder
 // coefficient r_(m-1-b) (plus the parity read, for decode and update); for
-// M = 4 the state is still rotated by the lane's phase g (byte b at b + g).
+// M = 4 the state is still rotated by the lane's phase g (byte b at b + g),
+// and likewise in the interleaved layout (byte b at position (b + g) / 2 of
+// dword b & 1).
 // Decode maps it through the apply tables; the result is transposed back to
 // blocks and stored: encode and update write parity p_(m-1-b) from byte b,
 // decode writes erased block e from byte e.
@@ -894,7 +898,8 @@ __device__ __forceinline__ void finish_chunk(const Src &src, uint32_t col, bool 
   if constexpr (op_of(MODE) == kDecode) {
     // Column by column: every lane walks all M tables (those past m are
     // zero) in its rotated order, and the M products are summed three at a
-    // time (v_bitop3_b32).  Two columns at a time: an empty asm that takes
+    // time (v_bitop3_b32).  Other than in the interleaved layout (below),
+    // two columns at a time: an empty asm that takes
     // and gives back the states of a pair of columns before and after their
     // lookups keeps the pairs in order; left free, the compiler issues the
     // lookups of every column at once and holds all their results
