@@ -69,8 +69,9 @@ LaunchCfg default_cfg(Mode mode, int sb, uint64_t B, int min_align, int num_cu) 
     while (w > 1 && (B + 4 * w - 1) / (4 * w) < want_lanes) w /= 2;
     cfg.dwords_per_lane = w;
   }
-  // Wide codes: 1024 threads, so that the decode (one workgroup per CU for
-  // its 128 KiB of tables) still has four waves per SIMD.
+  // Wide codes: 1024 threads, so that a kernel that runs one workgroup per
+  // CU (the decode's 128 KiB of tables; every 16-byte-per-lane kernel's
+  // 128-144 KiB in the interleaved layout) still has four waves per SIMD.
   const int tmax = codec_max_threads(mode, sb, cfg.dwords_per_lane);
   cfg.threads = sb == 8 ? tmax : std::min(512, tmax);
   const uint64_t cols = 4ull * cfg.dwords_per_lane;

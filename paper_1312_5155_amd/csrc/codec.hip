@@ -166,8 +166,9 @@ __device__ __forceinline__ void st4(uint8_t *lds, uint32_t off, uint32_t a, uint
 // bytes), each kLfsrReps replicas wide.  Decode of m <= 4: the same copies
 // at half the replication in bytes 0..127 and the apply tables U'_b (one
 // per remainder byte) in bytes 128..255.  Decode of m > 4 (8-byte entries)
-// needs whole rows for both, so its apply tables sit in a second 64 KiB
-// region (128 KiB of LDS, one workgroup per CU).
+// needs whole rows for both, so in the narrower kernels its apply tables sit
+// in a second 64 KiB region (128 KiB of LDS, one workgroup per CU); the
+// interleaved layout (below) has regions of its own.
 //
 // Split-nibble placement (the alternative the autotuner can pick): each
 // rotated copy of T' is two 16-entry tables, T'[n] in rows 0..15 and
