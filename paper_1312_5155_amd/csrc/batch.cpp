@@ -89,11 +89,13 @@ bool valid_launch(int op, int wide, const rs_poly_launch_t &c) {
 rs_poly_launch_t default_launch(int op, int wide) {
   rs_poly_launch_t c;
   if (wide) {
-    // RS(32,8), 64 x 32 x 16 MiB stripes: 16 bytes per lane and 1024
-    // threads (four waves per SIMD at 128 VGPRs) for every op
+    // RS(32,8), 64 x 32 x 16 MiB stripes: 16 bytes per lane.  Decode and
+    // update: 1024 threads (four waves per SIMD at 128 VGPRs), 64 KiB tiles.
+    // Encode: 512 threads and 16 KiB tiles, half the loads in flight per CU,
+    // measured 3.5-6% faster on three machines (A/B within one allocation).
     c.bytes_per_lane = 16;
-    c.threads = 1024;
-    c.tile_bytes = 64 << 10;
+    c.threads = op == RS_POLY_OP_ENCODE ? 512 : 1024;
+    c.tile_bytes = op == RS_POLY_OP_ENCODE ? 16 << 10 : 64 << 10;
   } else {
     c.bytes_per_lane = 16;
     c.threads = 512;
